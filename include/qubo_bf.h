@@ -1,0 +1,178 @@
+/*
+ * qubo_bf.h -- exhaustive QUBO solving in Gray-code order on MI355X (gfx950).
+ *
+ * Problem (Sec. 1, Eq. 1): for an upper-triangular Q in R^{n x n} (or Z^{n x n})
+ * and x in {0,1}^n,
+ *
+ *     f_Q(x) = x^T Q x = sum_{i <= j} Q_ij x_i x_j .
+ *
+ * The library visits all 2^n vectors (Sec. 2.2: reflected Gray code, bit CTZ(t)
+ * flipped at step t; Sec. 3.1: independent sub-walks under fixed prefix bits,
+ * min-combined) and returns the k lowest states.  The paper returns the single
+ * minimiser and its value (Algorithm 1); k > 1, batching and the log-partition
+ * function with its gradient are extensions with plain definitions given below.
+ *
+ * Conventions shared by every entry point:
+ *   - A state is a uint64 mask with bit i = x_i (0-based; x_1 of the paper is
+ *     bit 0), as in the decoding of Sec. 3.
+ *   - Only entries with i <= j are read (Eq. 1, right-hand side); the lower
+ *     triangle is ignored.  Q is row-major with leading dimension ldq.
+ *   - The zero vector is a candidate with value 0 (Sec. 2.1).
+ *   - Results are ordered by (energy, mask) ascending: equal energies go to the
+ *     lower natural mask (a reading; the paper does not state a tie rule).
+ *   - All array arguments are DEVICE pointers owned by the caller.  The library
+ *     allocates no device memory per call: scratch comes from the caller's
+ *     workspace `ws` of `ws_bytes` bytes (query the size first), which must stay
+ *     untouched until the call's work on `hip_stream` has completed.
+ *   - Every call only enqueues work on `hip_stream` (a hipStream_t; NULL = the
+ *     default stream) and returns without synchronising, so calls can be
+ *     captured into a HIP graph.  The return value reports host-checkable
+ *     errors only; conditions detected on the device are written to `status`
+ *     (int32 per instance, device memory) once the stream reaches that point.
+ *   - Calls that share a workspace must not overlap in time.
+ *   - qubo_last_error() describes the last non-OK return of the calling thread.
+ *
+ * Float semantics: float32 Q is enumerated with float32 table arithmetic; the
+ * K' >= k best candidates are rescored in float64 in a fixed order (row i
+ * ascending: Q_ii, then Q_ij for set j > i in ascending j; rows summed in
+ * ascending i) and selected by (float64 energy, mask).  A certificate proves
+ * that no state outside the candidates can rank among the k best; when it fails
+ * the outputs are still written and `status` is QUBO_ERR_UNCERTAIN.
+ * Integer semantics: int32 Q, exact int32 walk (requires sum_{i<=j} |Q_ij| <=
+ * 2^28, else status QUBO_ERR_RANGE), int64 energies, bit-exact results.
+ */
+#ifndef QUBO_BF_H
+#define QUBO_BF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { QUBO_F32 = 0, QUBO_I32 = 1 } qubo_dtype;
+
+enum {
+  QUBO_OK = 0,
+  QUBO_ERR_INVALID_ARG = -1, /* bad argument (host) or bad n in ns (device status) */
+  QUBO_ERR_NONFINITE = -2,   /* Q holds inf or NaN (device status) */
+  QUBO_ERR_WORKSPACE = -3,   /* ws_bytes smaller than the workspace query */
+  QUBO_ERR_HIP = -4,         /* a HIP launch or runtime call failed */
+  QUBO_ERR_UNCERTAIN = -5,   /* float certificate failed (device status) */
+  QUBO_ERR_RANGE = -6,       /* int32 Q with sum |Q_ij| > 2^28 (device status) */
+  QUBO_ERR_OVERFLOW = -7     /* internal slot overflow (device status; a bug) */
+};
+
+/* ------------------------------------------------------------------ top-k */
+
+/* Workspace bytes needed by qubo_bf_solve(n, k, dt); 0 for invalid arguments.
+ * Depends only on the arguments and the current tuning (qubo_bf_set_tuning). */
+size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt);
+
+/*
+ * The k lowest states of one QUBO (Algorithm 1 generalised from k = 1).
+ *   Q         device, n x n (ldq >= n), float32 (QUBO_F32) or int32 (QUBO_I32)
+ *   n         1 .. 63
+ *   k         1 .. 64 (int32), 1 .. 56 (float32)
+ *   energies  device, k entries: double (QUBO_F32) or int64_t (QUBO_I32);
+ *             slots beyond 2^n hold +inf / INT64_MAX
+ *   masks     device, k entries; slots beyond 2^n hold ~0
+ *   status    device, 1 int32: QUBO_OK, QUBO_ERR_NONFINITE, QUBO_ERR_RANGE or
+ *             QUBO_ERR_UNCERTAIN
+ * Returns QUBO_OK, QUBO_ERR_INVALID_ARG, QUBO_ERR_WORKSPACE or QUBO_ERR_HIP.
+ */
+int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
+                  int32_t* status, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Workspace bytes for qubo_bf_solve_batched with every n_b <= nmax. */
+size_t qubo_bf_batched_workspace_size(int batch, int nmax, int k, qubo_dtype dt);
+
+/*
+ * Independent solves of `batch` QUBOs of uneven size in one launch sequence.
+ *   Q         device, [batch][nmax][nmax]; instance b uses its leading
+ *             ns[b] x ns[b] block (row stride nmax)
+ *   nmax      1 .. 40
+ *   ns        device, [batch] sizes, 1 .. nmax (others: status INVALID_ARG)
+ *   energies  device, [batch][k]: double or int64_t (as qubo_bf_solve)
+ *   masks     device, [batch][k]
+ *   status    device, [batch]
+ * Returns as qubo_bf_solve.
+ */
+int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns, qubo_dtype dt, int k,
+                          void* energies, uint64_t* masks, int32_t* status, void* ws, size_t ws_bytes,
+                          void* hip_stream);
+
+/* ------------------------------------------------------- log-partition */
+
+/* Workspace bytes for qubo_logz_fwd / qubo_logz_bwd (the larger of the two). */
+size_t qubo_logz_workspace_size(int batch, int nmax);
+
+/*
+ * logZ_b = log sum_x exp(-beta_b f_{Q_b}(x)), natural log, float64 result.
+ *   Q      device, [batch][nmax][nmax] float32, sizes ns (device, [batch])
+ *   nmax   1 .. 32
+ *   beta   device, [batch] float32, any finite value
+ *   logz   device, [batch] double
+ *   status device, [batch]
+ */
+int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, double* logz,
+                  int32_t* status, void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Adjoint of qubo_logz_fwd, by re-enumeration:
+ *   grad_Q[b][i][j] = grad_logz[b] * (-beta_b) * E_p[x_i x_j]  for i <= j < n_b,
+ *   0 elsewhere (lower triangle and padding), p(x) = exp(-beta f(x) - logZ);
+ *   grad_beta[b] = grad_logz[b] * (-E_p[f])  (skipped when grad_beta is NULL).
+ *   logz   device, [batch] double, the forward result for the same inputs
+ *   grad_logz device, [batch] float32
+ *   grad_Q device, [batch][nmax][nmax] float32 (fully written)
+ */
+int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, const double* logz,
+                  const float* grad_logz, float* grad_Q, float* grad_beta, int32_t* status, void* ws,
+                  size_t ws_bytes, void* hip_stream);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Thread-local description of the last non-OK return (never NULL). */
+const char* qubo_last_error(void);
+/* Library version string. */
+const char* qubo_version(void);
+
+/*
+ * Tuning knobs (process-wide; 0 restores the default).  They change the
+ * workspace size, so query it again after a change.
+ *   QUBO_TUNE_SINGLE_OUTER_BITS   max outer (Gray-walked) bits per work unit, single solve
+ *   QUBO_TUNE_SINGLE_UNIT_BITS    prefix bits reserved for work units, single solve
+ *   QUBO_TUNE_BATCHED_OUTER_BITS  max outer bits per work unit, batched / logZ
+ *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
+ *   QUBO_TUNE_KPRIME              candidate list length override (float path;
+ *                                 values below k make the certificate fail)
+ * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)
+ * set the initial values.  Returns QUBO_OK or QUBO_ERR_INVALID_ARG.
+ */
+enum {
+  QUBO_TUNE_SINGLE_OUTER_BITS = 1,
+  QUBO_TUNE_SINGLE_UNIT_BITS = 2,
+  QUBO_TUNE_BATCHED_OUTER_BITS = 3,
+  QUBO_TUNE_WAVES_PER_CU = 4,
+  QUBO_TUNE_KPRIME = 5
+};
+int qubo_bf_set_tuning(int knob, int value);
+int qubo_bf_get_tuning(int knob);
+
+/*
+ * Kernel timing for measurement: while enabled, the library records a HIP
+ * event pair around each launch of its enumeration kernels on the call's
+ * stream.  qubo_prof_collect waits for the recorded events, returns the summed
+ * milliseconds and launch count of the kernel `name` ("walk_topk", "walk_exp",
+ * "walk_grad") and clears the records of that kernel.
+ */
+int qubo_prof_enable(int on);
+int qubo_prof_collect(const char* name, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUBO_BF_H */

@@ -1,0 +1,210 @@
+"""Python surface over the C ABI: device memory and streams come from PyTorch,
+every computation runs in the HIP library.
+
+* ``solve(Q, k)``                   k lowest states of one QUBO
+* ``solve_batched(Qpad, ns, k)``    k lowest states of many QUBOs, one launch sequence
+* ``BatchedSolver``                 the same with persistent buffers and optional
+                                    HIP-graph capture/replay
+* ``logz(Q, beta)``                 exact log-partition function, differentiable
+* ``masks_to_bits(masks, n)``       uint64 masks (bit i = x_i) -> 0/1 matrix
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import QuboError
+
+__all__ = ["solve", "solve_batched", "BatchedSolver", "logz", "LogZ", "masks_to_bits", "QuboError",
+           "UncertainError"]
+
+
+class UncertainError(QuboError):
+    """The float certificate could not prove the selection (ties closer than
+    the float32 rounding bound)."""
+
+
+_STATUS = {
+    _lib.QUBO_ERR_INVALID_ARG: "invalid instance size",
+    _lib.QUBO_ERR_NONFINITE: "Q holds inf or NaN",
+    _lib.QUBO_ERR_UNCERTAIN: "float certificate failed",
+    _lib.QUBO_ERR_RANGE: "int32 Q with sum |Q_ij| > 2^28",
+    _lib.QUBO_ERR_OVERFLOW: "internal candidate slot overflow",
+}
+
+
+def _as_device(x, dtype=None, device=None):
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(x)
+    dev = device if device is not None else (x.device if x.is_cuda else torch.device("cuda", torch.cuda.current_device()))
+    if dtype is not None and x.dtype != dtype:
+        x = x.to(dtype)
+    return x.to(dev).contiguous()
+
+
+def _qdtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return _lib.QUBO_F32
+    if t.dtype == torch.int32:
+        return _lib.QUBO_I32
+    raise TypeError("Q must be float32 or int32")
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _raise_status(status: torch.Tensor):
+    st = status.cpu().numpy()
+    bad = np.nonzero(st != 0)[0]
+    if bad.size:
+        code = int(st[bad[0]])
+        msg = f"{_STATUS.get(code, 'error')} (instance {int(bad[0])}, {bad.size} affected)"
+        if code == _lib.QUBO_ERR_UNCERTAIN:
+            raise UncertainError(code, msg)
+        raise QuboError(code, msg)
+
+
+def _check_upper(Q: torch.Tensor):
+    if torch.any(torch.tril(Q, -1) != 0).item():
+        raise ValueError("Q must be upper triangular (entries below the diagonal are nonzero)")
+
+
+def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = True):
+    """The k lowest states of f_Q(x) = x^T Q x over x in {0,1}^n.
+
+    Q: (n, n) float32 or int32 tensor/array, upper triangular.
+    Returns (energies, masks) on Q's GPU: float64 (float Q) or int64 (int Q),
+    and int64 tensors holding the uint64 masks (bit i = x_i), ascending by
+    (energy, mask).  Slots beyond 2^n hold +inf / INT64_MAX and mask -1.
+    """
+    Qd = _as_device(Q)
+    if Qd.ndim != 2 or Qd.shape[0] != Qd.shape[1]:
+        raise ValueError("Q must be square")
+    if check_lower:
+        _check_upper(Qd)
+    n = Qd.shape[0]
+    dt = _qdtype(Qd)
+    L = _lib.lib()
+    ws_bytes = L.qubo_bf_workspace_size(n, k, dt)
+    if ws_bytes == 0:
+        raise ValueError(f"invalid arguments n={n}, k={k}: {_lib.last_error()}")
+    dev = Qd.device
+    with torch.cuda.device(dev):
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=dev)
+        masks = torch.empty(k, dtype=torch.int64, device=dev)
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+        _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, n, dt, k, en.data_ptr(), masks.data_ptr(), status.data_ptr(),
+                                   ws.data_ptr(), ws_bytes, _stream(dev)))
+        try:
+            _raise_status(status)
+        except UncertainError:
+            if not retry_uncertain or dt != _lib.QUBO_F32:
+                raise
+            old = _lib.get_tuning(_lib.TUNE_KPRIME)
+            _lib.set_tuning(_lib.TUNE_KPRIME, 64)
+            try:
+                return solve(Qd, k, check_lower=False, retry_uncertain=False)
+            finally:
+                _lib.set_tuning(_lib.TUNE_KPRIME, old)
+    return en, masks
+
+
+class BatchedSolver:
+    """Persistent buffers for repeated batched solves of one shape.
+
+    ``run()`` enqueues the library's launch sequence; with ``graph=True`` the
+    sequence is captured once into a HIP graph (no allocation, no host sync,
+    no memset nodes inside) and later calls replay it.
+    """
+
+    def __init__(self, batch: int, nmax: int, k: int = 1, dtype=torch.float32, device=None, graph: bool = False):
+        self.batch, self.nmax, self.k = batch, nmax, k
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.dt = _lib.QUBO_F32 if dtype == torch.float32 else _lib.QUBO_I32
+        L = _lib.lib()
+        self.ws_bytes = L.qubo_bf_batched_workspace_size(batch, nmax, k, self.dt)
+        if self.ws_bytes == 0:
+            raise ValueError(f"invalid arguments: {_lib.last_error()}")
+        d = self.device
+        self.Q = torch.zeros((batch, nmax, nmax), dtype=dtype, device=d)
+        self.ns = torch.zeros(batch, dtype=torch.int32, device=d)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
+        self.energies = torch.empty((batch, k), dtype=torch.float64 if self.dt == _lib.QUBO_F32 else torch.int64,
+                                    device=d)
+        self.masks = torch.empty((batch, k), dtype=torch.int64, device=d)
+        self.status = torch.empty(batch, dtype=torch.int32, device=d)
+        self.use_graph = graph
+        self.graph = None
+
+    def load(self, Qpad, ns):
+        self.Q.copy_(_as_device(Qpad, self.Q.dtype, self.device))
+        self.ns.copy_(_as_device(ns, torch.int32, self.device))
+
+    def _enqueue(self):
+        L = _lib.lib()
+        _lib.check(L.qubo_bf_solve_batched(self.batch, self.Q.data_ptr(), self.nmax, self.ns.data_ptr(), self.dt,
+                                           self.k, self.energies.data_ptr(), self.masks.data_ptr(),
+                                           self.status.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                           _stream(self.device)))
+
+    def run(self):
+        with torch.cuda.device(self.device):
+            if not self.use_graph:
+                self._enqueue()
+                return
+            if self.graph is None:
+                s = torch.cuda.Stream(self.device)
+                s.wait_stream(torch.cuda.current_stream(self.device))
+                with torch.cuda.stream(s):
+                    self._enqueue()  # warm-up outside capture (loads modules)
+                torch.cuda.current_stream(self.device).wait_stream(s)
+                torch.cuda.synchronize(self.device)
+                self.graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(self.graph):
+                    self._enqueue()
+            self.graph.replay()
+
+    def results(self, check: bool = True):
+        if check:
+            _raise_status(self.status)
+        return self.energies, self.masks
+
+
+def solve_batched(Qpad, ns, k: int = 1, *, check_lower: bool = True):
+    """Independent k-lowest solves of many QUBOs.
+
+    Qpad: (batch, nmax, nmax) float32/int32, instance b in Qpad[b, :ns[b], :ns[b]].
+    Returns (energies [batch, k], masks [batch, k]) on the GPU.
+    """
+    Qd = _as_device(Qpad)
+    if Qd.ndim != 3 or Qd.shape[1] != Qd.shape[2]:
+        raise ValueError("Qpad must be (batch, nmax, nmax)")
+    if check_lower:
+        _check_upper(Qd)
+    nsd = _as_device(ns, torch.int32, Qd.device)
+    batch, nmax = Qd.shape[0], Qd.shape[1]
+    solver = BatchedSolver(batch, nmax, k, Qd.dtype, Qd.device)
+    solver.Q = Qd
+    solver.ns = nsd
+    solver.run()
+    return solver.results()
+
+
+def masks_to_bits(masks, n: int) -> np.ndarray:
+    """(..., ) uint64/int64 masks -> (..., n) uint8 matrix with x_i = bit i."""
+    if isinstance(masks, torch.Tensor):
+        masks = masks.detach().cpu().numpy()
+    m = np.asarray(masks).astype(np.uint64)
+    return ((m[..., None] >> np.arange(n, dtype=np.uint64)) & np.uint64(1)).astype(np.uint8)
+
+
+def logz(Q, beta):
+    raise NotImplementedError("log-partition entry points are not built yet")
+
+
+LogZ = None

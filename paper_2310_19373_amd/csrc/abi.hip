@@ -1,0 +1,395 @@
+// C ABI of the library: argument validation (before any HIP call), workspace
+// layout, tuning, kernel launch composition on the caller's stream.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "qubo_bf.h"
+
+using namespace qbf;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(QUBO_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------ tuning
+
+constexpr int kMaxGridWaves = 8192;  // sizing bound of the persistent grid
+
+struct Tuning {
+  int single_outer = 12;
+  int single_unit = 12;
+  int batched_outer = 8;
+  int waves_per_cu = 8;
+  int kprime = 0;
+};
+
+int env_int(const char* name, int dflt) {
+  const char* s = getenv(name);
+  if (!s || !*s) return dflt;
+  return atoi(s);
+}
+
+Tuning& tuning() {
+  static Tuning t = [] {
+    Tuning d;
+    d.single_outer = env_int("QUBO_BF_SINGLE_OUTER_BITS", d.single_outer);
+    d.single_unit = env_int("QUBO_BF_SINGLE_UNIT_BITS", d.single_unit);
+    d.batched_outer = env_int("QUBO_BF_BATCHED_OUTER_BITS", d.batched_outer);
+    d.waves_per_cu = env_int("QUBO_BF_WAVES_PER_CU", d.waves_per_cu);
+    d.kprime = env_int("QUBO_BF_KPRIME", d.kprime);
+    return d;
+  }();
+  return t;
+}
+
+int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+int kprime_for(int k, bool is_int) {
+  if (is_int) return k;
+  const int o = tuning().kprime;
+  if (o > 0) return clampi(o, 1, kMaxKPrime);
+  int kp = 2 * k > k + 8 ? 2 * k : k + 8;
+  return kp > kMaxKPrime ? kMaxKPrime : kp;
+}
+
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cache[dev] = c;
+  }
+  return cache[dev];
+}
+
+int grid_waves() {
+  long w = (long)device_cus() * clampi(tuning().waves_per_cu, 1, 32);
+  if (w > kMaxGridWaves) w = kMaxGridWaves;
+  return (int)(w - w % kWavesPerBlock);
+}
+
+// ------------------------------------------------------------- profiling
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  const char* name;
+  ProfScope(const char* nm, hipStream_t st) : s(st), name(nm) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back({name, a, b});
+  }
+};
+
+// ------------------------------------------------------------- workspace
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct SplitH {
+  int B, L, no, tb;
+};
+
+SplitH split_host(int n, const PlanParams& pp) {
+  SplitH s;
+  s.B = n < pp.inner ? n : pp.inner;
+  s.L = (n - s.B) < pp.lane_bits ? (n - s.B) : pp.lane_bits;
+  const int rest = n - s.B - s.L;
+  s.no = clampi(rest - pp.ub_min, 0, pp.no_max);
+  s.tb = rest - s.no;
+  return s;
+}
+
+struct Layout {
+  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, slots, part, total;
+};
+
+// Worst case over n <= nmax (steps and units grow with n).
+Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_unit, int64_t part_per_inst) {
+  const SplitH s = split_host(nmax, pp);
+  const int64_t steps = int64_t(1) << s.no;
+  const int64_t units = int64_t(1) << s.tb;
+  const int64_t slots = units < kMaxGridWaves ? units : kMaxGridWaves;
+  const int width = 1 << pp.inner;
+  Layout L;
+  size_t o = 0;
+  L.hdr = o;
+  o += al(sizeof(Header));
+  L.inst = o;
+  o += al(sizeof(Inst) * (size_t)batch);
+  L.gthr = o;
+  o += al(8 * (size_t)batch);
+  L.flush = o;
+  o += al(4 * (size_t)batch);
+  L.qs = o;
+  o += al(8 * (size_t)batch * nmax * nmax);
+  L.ei = o;
+  o += al(8 * (size_t)batch * 64);
+  L.tab = o;
+  o += al(4 * (size_t)batch * steps * width);
+  L.rec = o;
+  o += al(sizeof(StepRec) * (size_t)batch * steps);
+  L.slots = o;
+  o += al(sizeof(Slot) * (size_t)batch * slots * pp.kprime);
+  L.part = o;
+  o += al(8 * (size_t)batch * (units * part_per_unit + part_per_inst));
+  L.total = o;
+  return L;
+}
+
+Views make_views(void* ws, const Layout& L, int batch, int nmax) {
+  char* p = (char*)ws;
+  Views v;
+  v.hdr = (Header*)(p + L.hdr);
+  v.inst = (Inst*)(p + L.inst);
+  v.gthr = (uint64_t*)(p + L.gthr);
+  v.flushcnt = (uint32_t*)(p + L.flush);
+  v.qs = p + L.qs;
+  v.ei = p + L.ei;
+  v.tab = p + L.tab;
+  v.rec = (StepRec*)(p + L.rec);
+  v.slots = (Slot*)(p + L.slots);
+  v.part = (double*)(p + L.part);
+  v.batch = batch;
+  v.nmax = nmax;
+  return v;
+}
+
+PlanParams single_params(int kp) {
+  const Tuning& t = tuning();
+  PlanParams pp;
+  pp.no_max = clampi(t.single_outer, 0, kMaxOuter);
+  pp.ub_min = clampi(t.single_unit, 0, 62);
+  pp.inner = kInner;
+  pp.kprime = kp;
+  pp.waves = kMaxGridWaves;  // replaced by the real grid at launch
+  pp.lane_bits = 6;
+  return pp;
+}
+
+PlanParams batched_params(int kp) {
+  const Tuning& t = tuning();
+  PlanParams pp;
+  pp.no_max = clampi(t.batched_outer, 0, kMaxOuter);
+  pp.ub_min = 0;
+  pp.inner = kInner;
+  pp.kprime = kp;
+  pp.waves = kMaxGridWaves;
+  pp.lane_bits = 6;
+  return pp;
+}
+
+bool valid_dtype(qubo_dtype dt) { return dt == QUBO_F32 || dt == QUBO_I32; }
+
+int check_k(int k, bool is_int) {
+  if (k < 1 || k > kMaxKPrime) return fail(QUBO_ERR_INVALID_ARG, "k=%d outside [1, %d]", k, kMaxKPrime);
+  if (!is_int && k > kMaxKPrime - 8)
+    return fail(QUBO_ERR_INVALID_ARG, "k=%d outside [1, %d] for float32 Q", k, kMaxKPrime - 8);
+  return QUBO_OK;
+}
+
+// Enqueue plan -> prep -> tables -> walk -> finalize for a top-k call.
+int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const int32_t* ns, int n_single,
+             bool is_int, int k, PlanParams pp, int64_t units_hint, int64_t steps_hint, void* energies,
+             uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
+  int waves = grid_waves();
+  if (units_hint > 0 && units_hint < waves) {
+    waves = (int)units_hint;
+    waves += (kWavesPerBlock - waves % kWavesPerBlock) % kWavesPerBlock;
+  }
+  pp.waves = waves;
+  HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
+  HIPCHK(launch_prep_inst(v, Q, ldq, stride, is_int, kInner, s));
+  int tw = (int)(steps_hint < 4096 ? steps_hint : 4096);
+  HIPCHK(launch_prep_tables(v, is_int, kInner, tw < 4 ? 4 : tw, s));
+  {
+    ProfScope ps("walk_topk", s);
+    HIPCHK(launch_walk_topk(v, is_int, waves, s));
+  }
+  HIPCHK(launch_finalize_topk(v, Q, ldq, stride, is_int, k, energies, masks, status, fin_waves, s));
+  return QUBO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qubo_last_error(void) { return g_err.c_str(); }
+
+const char* qubo_version(void) { return "qubo_bf 0.1.0 gfx950"; }
+
+int qubo_bf_set_tuning(int knob, int value) {
+  Tuning& t = tuning();
+  const Tuning d;
+  switch (knob) {
+    case QUBO_TUNE_SINGLE_OUTER_BITS: t.single_outer = value > 0 ? clampi(value, 0, kMaxOuter) : d.single_outer; break;
+    case QUBO_TUNE_SINGLE_UNIT_BITS: t.single_unit = value > 0 ? clampi(value, 0, 62) : d.single_unit; break;
+    case QUBO_TUNE_BATCHED_OUTER_BITS: t.batched_outer = value > 0 ? clampi(value, 0, kMaxOuter) : d.batched_outer; break;
+    case QUBO_TUNE_WAVES_PER_CU: t.waves_per_cu = value > 0 ? clampi(value, 1, 32) : d.waves_per_cu; break;
+    case QUBO_TUNE_KPRIME: t.kprime = value > 0 ? clampi(value, 1, kMaxKPrime) : 0; break;
+    default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
+  }
+  return QUBO_OK;
+}
+
+int qubo_bf_get_tuning(int knob) {
+  const Tuning& t = tuning();
+  switch (knob) {
+    case QUBO_TUNE_SINGLE_OUTER_BITS: return t.single_outer;
+    case QUBO_TUNE_SINGLE_UNIT_BITS: return t.single_unit;
+    case QUBO_TUNE_BATCHED_OUTER_BITS: return t.batched_outer;
+    case QUBO_TUNE_WAVES_PER_CU: return t.waves_per_cu;
+    case QUBO_TUNE_KPRIME: return t.kprime;
+    default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
+  }
+}
+
+int qubo_prof_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return QUBO_OK;
+}
+
+int qubo_prof_collect(const char* name, double* total_ms, int64_t* launches) {
+  if (!name || !total_ms || !launches) return fail(QUBO_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  double ms = 0.0;
+  int64_t cnt = 0;
+  std::vector<ProfRec> keep;
+  for (auto& r : g_prof) {
+    if (r.name != name) {
+      keep.push_back(r);
+      continue;
+    }
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      return fail(QUBO_ERR_HIP, "event timing failed");
+    ms += t;
+    ++cnt;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.swap(keep);
+  *total_ms = ms;
+  *launches = cnt;
+  return QUBO_OK;
+}
+
+size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt) {
+  if (n < 1 || n > 63 || !valid_dtype(dt)) return 0;
+  const bool is_int = dt == QUBO_I32;
+  if (check_k(k, is_int) != QUBO_OK) return 0;
+  return make_layout(1, n, single_params(kprime_for(k, is_int)), 0, 0).total;
+}
+
+int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
+                  int32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!Q || !energies || !masks || !status || !ws) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (n < 1 || n > 63) return fail(QUBO_ERR_INVALID_ARG, "n=%d outside [1, 63]", n);
+  if (ldq < n) return fail(QUBO_ERR_INVALID_ARG, "ldq=%lld < n=%d", (long long)ldq, n);
+  if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+  const bool is_int = dt == QUBO_I32;
+  if (int rc = check_k(k, is_int)) return rc;
+  const int kp = kprime_for(k, is_int);
+  const PlanParams pp = single_params(kp);
+  const Layout L = make_layout(1, n, pp, 0, 0);
+  if (ws_bytes < L.total)
+    return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+  const Views v = make_views(ws, L, 1, n);
+  const SplitH sh = split_host(n, pp);
+  return run_topk(v, Q, ldq, 0, nullptr, n, is_int, k, pp, int64_t(1) << sh.tb, int64_t(1) << sh.no, energies,
+                  masks, status, 16, (hipStream_t)hip_stream);
+}
+
+size_t qubo_bf_batched_workspace_size(int batch, int nmax, int k, qubo_dtype dt) {
+  if (batch < 1 || nmax < 1 || nmax > 40 || !valid_dtype(dt)) return 0;
+  const bool is_int = dt == QUBO_I32;
+  if (check_k(k, is_int) != QUBO_OK) return 0;
+  return make_layout(batch, nmax, batched_params(kprime_for(k, is_int)), 0, 0).total;
+}
+
+int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns, qubo_dtype dt, int k,
+                          void* energies, uint64_t* masks, int32_t* status, void* ws, size_t ws_bytes,
+                          void* hip_stream) {
+  if (!Q || !ns || !energies || !masks || !status || !ws) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (batch < 1) return fail(QUBO_ERR_INVALID_ARG, "batch=%d < 1", batch);
+  if (nmax < 1 || nmax > 40) return fail(QUBO_ERR_INVALID_ARG, "nmax=%d outside [1, 40]", nmax);
+  if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+  const bool is_int = dt == QUBO_I32;
+  if (int rc = check_k(k, is_int)) return rc;
+  const int kp = kprime_for(k, is_int);
+  const PlanParams pp = batched_params(kp);
+  const Layout L = make_layout(batch, nmax, pp, 0, 0);
+  if (ws_bytes < L.total)
+    return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+  const Views v = make_views(ws, L, batch, nmax);
+  const SplitH sh = split_host(nmax, pp);
+  const int64_t steps_bound = (int64_t)batch << sh.no;
+  return run_topk(v, Q, nmax, (int64_t)nmax * nmax, ns, 0, is_int, k, pp, 0, steps_bound, energies, masks,
+                  status, 1, (hipStream_t)hip_stream);
+}
+
+size_t qubo_logz_workspace_size(int batch, int nmax) {
+  (void)batch;
+  (void)nmax;
+  return 0;
+}
+
+int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, double* logz,
+                  int32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
+  (void)batch; (void)Q; (void)nmax; (void)ns; (void)beta; (void)logz; (void)status; (void)ws; (void)ws_bytes;
+  (void)hip_stream;
+  return fail(QUBO_ERR_INVALID_ARG, "qubo_logz_fwd: not available in this build");
+}
+
+int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, const double* logz,
+                  const float* grad_logz, float* grad_Q, float* grad_beta, int32_t* status, void* ws,
+                  size_t ws_bytes, void* hip_stream) {
+  (void)batch; (void)Q; (void)nmax; (void)ns; (void)beta; (void)logz; (void)grad_logz; (void)grad_Q;
+  (void)grad_beta; (void)status; (void)ws; (void)ws_bytes; (void)hip_stream;
+  return fail(QUBO_ERR_INVALID_ARG, "qubo_logz_bwd: not available in this build");
+}
+
+}  // extern "C"

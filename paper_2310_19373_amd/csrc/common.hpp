@@ -1,0 +1,112 @@
+// Shared device/host definitions of the gfx950 QUBO enumeration library.
+//
+// Bit layout of a state (mask bit i = x_i, 0-based):
+//
+//   [0, B)              inner bits   j   : enumerated from a per-lane table
+//   [B, B+no)           outer bits   o   : walked in reflected Gray-code order
+//   [B+no, B+no+L)      lane bits        : one value per wavefront lane
+//   [B+no+L, n)         tile bits        : one value per work unit (wave task)
+//
+// The lane and tile bits together are the fixed prefix of Sec. 3.1: every
+// (unit, lane) pair owns an independent sub-walk over the lower bits.  The
+// energy of Eq. 1 splits exactly into
+//
+//   f(x) = C'(lane; j) + T'(o; j) + KE(lane; o)
+//     C'  = E_I(j) + X_PI(p, j)      per lane, fixed for the unit  (table)
+//     T'  = X_IO(j, o)                uniform over lanes, per step  (table)
+//     KE  = E_P(p) + X_PO(p, o) + E_O(o)   per lane, per step (scalar)
+//
+// where E_A is the objective restricted to the bits of group A and X_AB the
+// cross terms between groups A and B.  KE follows the Gray walk with the O(1)
+// update of Eq. 3 restricted to the prefix/outer cross terms; the inner bits
+// are never walked, each inner state costs one table addition.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qbf {
+
+constexpr int kWave = 64;
+constexpr int kInner = 6;                 // inner bits of the top-k / logZ-forward walks
+constexpr int kInnerStates = 1 << kInner;  // 64 table entries per lane
+constexpr int kMaxOuter = 20;              // outer bits per unit (per-lane LDS table bound)
+constexpr int kBlock = 256;                // threads per block of the walk kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxKPrime = 64;             // candidate list length (one entry per lane)
+constexpr int32_t kIntInvalid = 1 << 30;   // table sentinel of the int32 path
+constexpr int64_t kIntSumLimit = int64_t(1) << 28;  // int32 path: sum |Q| bound
+
+// status codes (mirrors include/qubo_bf.h)
+constexpr int32_t kOk = 0;
+constexpr int32_t kErrArg = -1;
+constexpr int32_t kErrNonfinite = -2;
+constexpr int32_t kErrUncertain = -5;
+constexpr int32_t kErrRange = -6;
+constexpr int32_t kErrOverflow = -7;
+
+// One instance of a (batched) call, written by the planner.
+struct Inst {
+  int32_t n, B, L, no, tb;  // bit split (see above)
+  int32_t kprime;           // candidate list length
+  int32_t status;           // device-detected status, 0 = OK
+  int32_t pad0;
+  int64_t units;            // 2^tb work units
+  int64_t unit_begin;       // first global unit index
+  int64_t tab_off;          // first step of this instance's tables
+  int64_t slot_off;         // first candidate-list slot
+  int64_t slot_cap;         // candidate-list slots available
+  double sumabs;            // sum |Q_ij| over i <= j
+  double big;               // threshold that no state exceeds
+  double eps;               // bound on |f32 walk value - exact value| (float path)
+  double sign;              // +1, or -1 when the walk runs on -Q
+};
+
+// Per-call header at the start of the workspace.
+struct Header {
+  uint64_t unit_counter;  // persistent work queue
+  uint64_t total_units;
+  int64_t total_steps;
+  int64_t total_slots;
+  int32_t batch;
+  int32_t nmax;
+  int32_t waves;          // waves of the persistent walk grid
+  int32_t pad;
+};
+
+// Per-step uniform data of the outer walk.
+struct StepRec {
+  double eo;      // E_O(g(t))
+  double h[6];    // H_u(g(t)) = sum_{v in O} S_uv x_v, u < 6
+  int32_t neo;    // -E_O(g(t)) for the int32 path
+  int32_t pad;
+};
+
+struct Slot {
+  double key;
+  uint64_t mask;
+};
+
+// Ordered encoding: a < b  <=>  enc(a) < enc(b) (for non-NaN doubles).
+__host__ __device__ inline uint64_t enc_key(double v) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ inline double dec_key(uint64_t u) {
+  uint64_t v = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+  return __builtin_bit_cast(double, v);
+}
+
+__host__ __device__ inline uint64_t gray(uint64_t t) { return t ^ (t >> 1); }
+
+// Global-memory pointers.  Pointers taken out of a by-value argument struct are
+// generic to the compiler; re-qualifying them lets it use global / scalar loads
+// and keep loop bounds loaded from them in SGPRs.
+#define QBF_GLOBAL __attribute__((address_space(1)))
+template <class T>
+using gptr = T QBF_GLOBAL*;
+template <class T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+  return (gptr<T>)p;
+}
+
+}  // namespace qbf

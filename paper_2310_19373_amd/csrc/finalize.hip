@@ -1,0 +1,153 @@
+// Merge of the flushed candidate lists, rescoring and the float certificate.
+//
+// One block per instance (W waves).  Each wave scans a share of the instance's
+// flushed lists, keeping its own sorted top-K' (filtered by the instance's
+// published threshold, which bounds the final K'-th key from above); wave 0
+// merges the others through LDS.  Wave 0 then recomputes every candidate's
+// energy from the input Q in a fixed order -- i ascending; for each set bit i
+// the row term starts at Q_ii and adds Q_ij for set j > i in ascending j; row
+// terms summed in ascending i -- in float64 (float Q) or int64 (int Q), sorts
+// by (energy, mask), writes the k best and, for float Q, checks the
+// certificate: every state outside the candidate set has an exact value of at
+// least thr - eps, where thr is the K'-th candidate key, so the selection is
+// exact when thr - eps exceeds the k-th rescored energy.
+#include <type_traits>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "wave.hpp"
+
+namespace qbf {
+
+namespace {
+
+template <class Qin>
+struct Rescore;
+template <>
+struct Rescore<float> {
+  using En = double;
+  __device__ static En sentinel() { return __builtin_inf(); }
+  __device__ static En energy(const float* Q, int64_t ldq, int n, uint64_t m) {
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (!((m >> i) & 1)) continue;
+      double row = (double)Q[(int64_t)i * ldq + i];
+      for (int j = i + 1; j < n; ++j)
+        if ((m >> j) & 1) row = __dadd_rn(row, (double)Q[(int64_t)i * ldq + j]);
+      tot = __dadd_rn(tot, row);
+    }
+    return tot;
+  }
+};
+template <>
+struct Rescore<int32_t> {
+  using En = int64_t;
+  __device__ static En sentinel() { return INT64_MAX; }
+  __device__ static En energy(const int32_t* Q, int64_t ldq, int n, uint64_t m) {
+    int64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!((m >> i) & 1)) continue;
+      int64_t row = Q[(int64_t)i * ldq + i];
+      for (int j = i + 1; j < n; ++j)
+        if ((m >> j) & 1) row += Q[(int64_t)i * ldq + j];
+      tot += row;
+    }
+    return tot;
+  }
+};
+
+__device__ __forceinline__ int64_t readlane_en(int64_t v, int l) { return readlane_i64(v, l); }
+__device__ __forceinline__ double readlane_en(double v, int l) { return readlane_f64(v, l); }
+
+constexpr int kMaxFinWaves = 16;
+
+template <class Qin>
+__global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin* q, int64_t ldq, int64_t stride,
+                                                             int k, typename Rescore<Qin>::En* energies,
+                                                             uint64_t* masks, int32_t* status) {
+  using En = typename Rescore<Qin>::En;
+  __shared__ double sk[kMaxFinWaves][kWave];
+  __shared__ uint64_t sm[kMaxFinWaves][kWave];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const Inst* I = &v.inst[b];
+  const int kp = I->kprime;
+  const int32_t st0 = I->status;
+  double lkey = __builtin_inf();
+  uint64_t lmask = ~0ull;
+  if (st0 == 0) {
+    const int64_t cnt = min<int64_t>((int64_t)v.flushcnt[b], I->slot_cap);
+    const int64_t total = cnt * kp;
+    const Slot* sl = v.slots + I->slot_off * kp;
+    double thr = fmin(dec_key(v.gthr[b]), I->big);
+    for (int64_t base = (int64_t)w * kWave; base < total; base += (int64_t)nw * kWave) {
+      const int64_t e = base + lane;
+      double key = __builtin_inf();
+      uint64_t m = ~0ull;
+      if (e < total) {
+        key = sl[e].key;
+        m = sl[e].mask;
+      }
+      uint64_t bal = ballot(key <= thr);
+      while (bal) {
+        const int src = __builtin_ctzll(bal);
+        bal &= bal - 1;
+        const double ck = readlane_f64(key, src);
+        if (ck <= thr && list_insert(lkey, lmask, ck, readlane_u64(m, src), kp, lane)) {
+          const double lt = readlane_f64(lkey, kp - 1);
+          if (lt < thr) thr = lt;
+        }
+      }
+    }
+  }
+  sk[w][lane] = lkey;
+  sm[w][lane] = lmask;
+  __syncthreads();
+  if (w != 0) return;
+  for (int o = 1; o < nw; ++o) {
+    const double ok = sk[o][lane];
+    const uint64_t om = sm[o][lane];
+    for (int i = 0; i < kp; ++i) {
+      const double ck = readlane_f64(ok, i);
+      if (!(ck < __builtin_inf())) break;
+      list_insert(lkey, lmask, ck, readlane_u64(om, i), kp, lane);
+    }
+  }
+  int32_t st = st0;
+  if (st == 0 && (int64_t)v.flushcnt[b] > I->slot_cap) st = kErrOverflow;
+  En en = Rescore<Qin>::sentinel();
+  uint64_t m = ~0ull;
+  if (st0 == 0 && lane < kp && lkey < __builtin_inf()) {
+    m = lmask;
+    en = Rescore<Qin>::energy(q + (int64_t)b * stride, ldq, I->n, m);
+  }
+  wave_sort(en, m, lane);
+  if constexpr (std::is_same_v<Qin, float>) {
+    const double thr_m = readlane_f64(lkey, kp - 1);
+    const double ek = readlane_en(en, k - 1);
+    if (st == 0 && I->eps > 0.0 && thr_m < __builtin_inf() && !(thr_m - I->eps > ek)) st = kErrUncertain;
+  }
+  if (lane < k) {
+    const bool ok = (st == 0 || st == kErrUncertain);
+    energies[(int64_t)b * k + lane] = ok ? en : Rescore<Qin>::sentinel();
+    masks[(int64_t)b * k + lane] = ok ? m : ~0ull;
+  }
+  if (lane == 0) status[b] = st;
+}
+
+}  // namespace
+
+hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t stride, bool is_int, int k,
+                                void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,
+                                hipStream_t s) {
+  const int w = max(1, min(kMaxFinWaves, waves_per_inst));
+  if (is_int)
+    hipLaunchKernelGGL(finalize_topk_kernel<int32_t>, dim3(v.batch), dim3(64 * w), 0, s, v, (const int32_t*)q, ldq,
+                       stride, k, (int64_t*)energies, masks, status);
+  else
+    hipLaunchKernelGGL(finalize_topk_kernel<float>, dim3(v.batch), dim3(64 * w), 0, s, v, (const float*)q, ldq,
+                       stride, k, (double*)energies, masks, status);
+  return hipGetLastError();
+}
+
+}  // namespace qbf

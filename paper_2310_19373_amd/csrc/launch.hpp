@@ -1,0 +1,63 @@
+// Host-side launchers of the kernels (one translation unit each); the C ABI
+// in abi.hip composes them on the caller's stream.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace qbf {
+
+// Device views of one call's workspace.
+struct Views {
+  Header* hdr;
+  Inst* inst;
+  uint64_t* gthr;
+  uint32_t* flushcnt;
+  void* qs;        // [batch][nmax][nmax] double (float path) or int64 (int path)
+  void* ei;        // [batch][64] double or int64
+  void* tab;       // [total_steps][2^inner] float or int32, row-broadcast layout
+  StepRec* rec;    // [total_steps]
+  Slot* slots;     // [total_slots][kprime]
+  double* part;    // per-unit partial sums (logZ forward) / per-wave moments (gradient)
+  int batch, nmax;
+};
+
+struct PlanParams {
+  int no_max;    // outer bits per unit, upper bound
+  int ub_min;    // unit bits wanted before outer bits are granted
+  int inner;     // inner bits of the walk (6 for top-k and logZ forward, 5 for the gradient)
+  int kprime;    // candidate list length
+  int waves;     // waves of the persistent walk grid
+  int lane_bits; // lane bits wanted (6 normally)
+};
+
+// plan: bit split, unit/table/slot offsets, counters.  ns == nullptr: one
+// instance of size n_single.  beta (may be null): instance sign = sign(beta).
+hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta,
+                       const PlanParams& pp, hipStream_t s);
+// prep: symmetric Q, sums, E_I table, float/int validation.
+hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
+                            int inner, hipStream_t s);
+// per-step tables of the outer walk.
+hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int grid_waves, hipStream_t s);
+// persistent top-k walk.
+hipError_t launch_walk_topk(const Views& v, bool is_int, int waves, hipStream_t s);
+// merge candidate lists, rescore in float64 / int64, certificate, outputs.
+hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
+                                int k, void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,
+                                hipStream_t s);
+
+// log-partition forward: min pass (walk_topk, k = 1) then exp pass.
+hipError_t launch_finalize_min(const Views& v, double* eref, hipStream_t s);
+hipError_t launch_walk_exp(const Views& v, const float* beta, const double* eref, int waves, hipStream_t s);
+hipError_t launch_finalize_logz(const Views& v, const float* beta, const double* eref, double* logz,
+                                int32_t* status, hipStream_t s);
+// log-partition backward: moment walk (inner = 5) then assembly.
+hipError_t launch_walk_grad(const Views& v, const float* beta, const double* logz, int64_t total_waves,
+                            int n_moments, hipStream_t s);
+hipError_t launch_finalize_grad(const Views& v, const float* q, const float* beta, const float* grad_logz,
+                                float* grad_q, float* grad_beta, int32_t* status, int n_moments,
+                                hipStream_t s);
+
+}  // namespace qbf

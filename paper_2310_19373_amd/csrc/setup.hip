@@ -1,0 +1,274 @@
+// Planner and table builders.
+//
+// plan_kernel    : bit split of every instance, work-unit / table / slot offsets,
+//                  queue and threshold reset (written by a kernel, so that a
+//                  captured graph replays it without memset nodes).
+// prep_inst      : symmetric copy of Q (the qua/lin split of Sec. 3: off-diagonal
+//                  S = triu(Q,1) + triu(Q,1)^T, diagonal d = diag(Q)), sum |Q|,
+//                  validation, and the inner-bit energies E_I(j).
+// prep_tables    : per outer Gray step t the uniform table T'(g(t); j) and the
+//                  scalars E_O(g(t)), H_u(g(t)).
+#include <math.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace qbf {
+
+namespace {
+
+struct Split {
+  int B, L, no, tb;
+  int64_t units, steps;
+};
+
+__device__ Split split_bits(int n, const PlanParams& pp) {
+  Split s;
+  s.B = min(pp.inner, n);
+  s.L = min(pp.lane_bits, n - s.B);
+  const int rest = n - s.B - s.L;
+  s.no = max(0, min(pp.no_max, rest - pp.ub_min));
+  s.tb = rest - s.no;
+  s.units = int64_t(1) << s.tb;
+  s.steps = int64_t(1) << s.no;
+  return s;
+}
+
+__global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, int n_single, const float* beta,
+                                                    PlanParams pp) {
+  __shared__ int64_t su[1024], ss[1024], sl[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int batch = v.batch;
+  const int per = (batch + nt - 1) / nt;
+  const int b0 = min(batch, tid * per), b1 = min(batch, b0 + per);
+  int64_t lu = 0, ls = 0, lsl = 0;
+  for (int b = b0; b < b1; ++b) {
+    const int n = ns ? ns[b] : n_single;
+    if (n < 1 || n > v.nmax || n > 63) continue;
+    const Split s = split_bits(n, pp);
+    lu += s.units;
+    ls += s.steps;
+    lsl += min<int64_t>(s.units, pp.waves);
+  }
+  su[tid] = lu;
+  ss[tid] = ls;
+  sl[tid] = lsl;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    int64_t a = 0, c = 0, d = 0;
+    if (tid >= off) {
+      a = su[tid - off];
+      c = ss[tid - off];
+      d = sl[tid - off];
+    }
+    __syncthreads();
+    su[tid] += a;
+    ss[tid] += c;
+    sl[tid] += d;
+    __syncthreads();
+  }
+  int64_t cu = su[tid] - lu, cs = ss[tid] - ls, csl = sl[tid] - lsl;
+  for (int b = b0; b < b1; ++b) {
+    const int n = ns ? ns[b] : n_single;
+    Inst I = {};
+    I.n = n;
+    I.kprime = pp.kprime;
+    I.sign = (beta && beta[b] < 0.0f) ? -1.0 : 1.0;
+    if (n < 1 || n > v.nmax || n > 63) {
+      I.status = kErrArg;
+      I.unit_begin = cu;
+      I.tab_off = cs;
+      I.slot_off = csl;
+    } else {
+      const Split s = split_bits(n, pp);
+      I.B = s.B;
+      I.L = s.L;
+      I.no = s.no;
+      I.tb = s.tb;
+      I.units = s.units;
+      I.unit_begin = cu;
+      I.tab_off = cs;
+      I.slot_off = csl;
+      I.slot_cap = min<int64_t>(s.units, pp.waves);
+      cu += s.units;
+      cs += s.steps;
+      csl += I.slot_cap;
+    }
+    v.inst[b] = I;
+    v.gthr[b] = enc_key(__builtin_inf());
+    v.flushcnt[b] = 0;
+  }
+  if (tid == nt - 1) {
+    v.hdr->unit_counter = 0;
+    v.hdr->total_units = (uint64_t)su[nt - 1];
+    v.hdr->total_steps = ss[nt - 1];
+    v.hdr->total_slots = sl[nt - 1];
+    v.hdr->batch = batch;
+    v.hdr->nmax = v.nmax;
+    v.hdr->waves = pp.waves;
+  }
+}
+
+template <class T>
+__device__ double absd(T x) {
+  return fabs((double)x);
+}
+
+template <class Qin, class W>
+__global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, int64_t ldq, int64_t stride,
+                                                        int inner) {
+  __shared__ double red_a[256], red_r[256];
+  __shared__ int red_bad[256], red_frac[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  Inst* I = &v.inst[b];
+  if (I->status != 0) return;
+  const int n = I->n, nmax = v.nmax, B = I->B;
+  const Qin* Q = q + (int64_t)b * stride;
+  W* qs = (W*)v.qs + (int64_t)b * nmax * nmax;
+  const double sgn = I->sign;
+  double sabs = 0.0, rI = 0.0;
+  int bad = 0, frac = 0;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    const Qin val = (i <= j) ? Q[(int64_t)i * ldq + j] : Q[(int64_t)j * ldq + i];
+    if constexpr (std::is_same_v<Qin, float>) {
+      if (!isfinite(val)) bad = 1;
+      if (i <= j && val != truncf(val)) frac = 1;
+    }
+    qs[(int64_t)i * nmax + j] = (W)(sgn * (double)val);
+    if (i <= j) sabs += absd(val);
+    if (i < B) rI += absd(val);
+  }
+  red_a[tid] = sabs;
+  red_r[tid] = rI;
+  red_bad[tid] = bad;
+  red_frac[tid] = frac;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      red_a[tid] += red_a[tid + off];
+      red_r[tid] += red_r[tid + off];
+      red_bad[tid] |= red_bad[tid + off];
+      red_frac[tid] |= red_frac[tid + off];
+    }
+    __syncthreads();
+  }
+  // E_I(j) for the inner bits, straight from Eq. 1 restricted to bits < B.
+  if (tid < (1 << inner)) {
+    W e = 0;
+    for (int u = 0; u < B; ++u) {
+      if (!((tid >> u) & 1)) continue;
+      W row = (W)(sgn * (double)Q[(int64_t)u * ldq + u]);
+      for (int w = u + 1; w < B; ++w)
+        if ((tid >> w) & 1) row += (W)(sgn * (double)Q[(int64_t)u * ldq + w]);
+      e += row;
+    }
+    ((W*)v.ei)[(int64_t)b * 64 + tid] = e;
+  }
+  if (tid == 0) {
+    const double sa = red_a[0];
+    I->sumabs = sa;
+    if constexpr (std::is_same_v<W, double>) {
+      I->big = sa * (1.0 + 1e-6) + 1.0;
+      // |f32 table value - exact| <= 2u * R_I with u = 2^-24 (C', T' and their sum
+      // are partial sums of the inner rows); the rest is float64 rounding.
+      I->eps = 3.0 * 0x1p-24 * red_r[0] + 1e-12 * sa;
+      // Integer-valued float Q with sum |Q| <= 2^24: every table value, sum and
+      // key is an integer below 2^24 in magnitude, exact in float32 and float64,
+      // so the walk is exact (eps = 0) and ties are resolved like the int path.
+      if (!red_frac[0] && sa <= 16777216.0) I->eps = 0.0;
+      if (red_bad[0]) I->status = kErrNonfinite;
+    } else {
+      I->big = sa + 1.0;
+      I->eps = 0.0;
+      if (sa > (double)kIntSumLimit) I->status = kErrRange;
+    }
+  }
+}
+
+__device__ int find_by_tab(const Views& v, int64_t s) {
+  int lo = 0, hi = v.batch;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (v.inst[mid].tab_off <= s) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <class W, class E>
+__global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t total = v.hdr->total_steps;
+  const int width = 1 << inner, per = width / 16;
+  for (int64_t s = wave; s < total; s += nwaves) {
+    const int b = v.batch == 1 ? 0 : find_by_tab(v, s);
+    const Inst* I = &v.inst[b];
+    const int64_t t = s - I->tab_off;
+    W H[6] = {0, 0, 0, 0, 0, 0};
+    W eo = 0;
+    const int B = I->B, no = I->no;
+    if (I->status == 0 && t < (int64_t(1) << no)) {
+      const W* qs = (const W*)v.qs + (int64_t)b * v.nmax * v.nmax;
+      const uint64_t o = gray((uint64_t)t);
+      for (int l = 0; l < no; ++l) {
+        if (!((o >> l) & 1)) continue;
+        const int a = B + l;
+        W row = qs[(int64_t)a * v.nmax + a];
+        for (int l2 = l + 1; l2 < no; ++l2)
+          if ((o >> l2) & 1) row += qs[(int64_t)a * v.nmax + B + l2];
+        eo += row;
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+          if (u < B) H[u] += qs[(int64_t)u * v.nmax + a];
+      }
+    }
+    W tj = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+      if (u < B && ((lane >> u) & 1)) tj += H[u];
+    if (lane < width) ((E*)v.tab)[s * width + (lane & 15) * per + (lane >> 4)] = (E)tj;
+    if (lane == 0) {
+      StepRec r;
+      r.eo = (double)eo;
+      for (int u = 0; u < 6; ++u) r.h[u] = (double)H[u];
+      r.neo = (int32_t)(-eo);
+      r.pad = 0;
+      v.rec[s] = r;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta, const PlanParams& pp,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, v, ns, n_single, beta, pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t stride, bool is_int, int inner,
+                            hipStream_t s) {
+  if (is_int)
+    hipLaunchKernelGGL((prep_inst_kernel<int32_t, int64_t>), dim3(v.batch), dim3(256), 0, s, v,
+                       (const int32_t*)q, ldq, stride, inner);
+  else
+    hipLaunchKernelGGL((prep_inst_kernel<float, double>), dim3(v.batch), dim3(256), 0, s, v, (const float*)q,
+                       ldq, stride, inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int grid_waves, hipStream_t s) {
+  const int blocks = max(1, grid_waves / 4);
+  if (is_int)
+    hipLaunchKernelGGL((prep_tables_kernel<int64_t, int32_t>), dim3(blocks), dim3(256), 0, s, v, inner);
+  else
+    hipLaunchKernelGGL((prep_tables_kernel<double, float>), dim3(blocks), dim3(256), 0, s, v, inner);
+  return hipGetLastError();
+}
+
+}  // namespace qbf

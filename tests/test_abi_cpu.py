@@ -1,0 +1,91 @@
+"""The C ABI library loads and exports every symbol include/qubo_bf.h declares;
+host-side argument validation answers before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2310_19373_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qubo_bf.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qubo_\w+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    fns = header_functions()
+    for name in ("qubo_bf_solve", "qubo_bf_solve_batched", "qubo_logz_fwd", "qubo_logz_bwd",
+                 "qubo_bf_workspace_size", "qubo_last_error"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+    assert set(header_functions()) == set(_lib.SIGNATURES)
+
+
+def test_version_and_error_string():
+    L = _lib.lib()
+    assert b"gfx950" in L.qubo_version()
+    assert isinstance(L.qubo_last_error(), bytes)
+
+
+def test_workspace_queries_validate():
+    L = _lib.lib()
+    assert L.qubo_bf_workspace_size(0, 1, 0) == 0
+    assert L.qubo_bf_workspace_size(64, 1, 0) == 0
+    assert L.qubo_bf_workspace_size(20, 0, 0) == 0
+    assert L.qubo_bf_workspace_size(20, 57, 0) == 0   # float k above 56
+    assert L.qubo_bf_workspace_size(20, 64, 1) > 0    # int k up to 64
+    assert L.qubo_bf_workspace_size(20, 1, 7) == 0    # bad dtype
+    assert L.qubo_bf_workspace_size(40, 16, 0) > L.qubo_bf_workspace_size(20, 16, 0)
+    assert L.qubo_bf_batched_workspace_size(4096, 28, 1, 0) > 0
+    assert L.qubo_bf_batched_workspace_size(4096, 41, 1, 0) == 0
+
+
+FAKE = 256  # a non-null dummy address: every case below is rejected before use
+
+
+@pytest.mark.parametrize("case,code", [
+    (dict(Q=None), -1), (dict(n=0), -1), (dict(n=64), -1), (dict(ldq=5), -1),
+    (dict(dt=3), -1), (dict(k=0), -1), (dict(k=57), -1), (dict(status=None), -1),
+    (dict(ws_bytes=16), -3),
+])
+def test_solve_rejects_before_any_hip_call(case, code):
+    L = _lib.lib()
+    a = dict(Q=FAKE, n=10, ldq=10, dt=0, k=4, en=FAKE, masks=FAKE, status=FAKE, ws=FAKE, ws_bytes=16, stream=None)
+    if code != -3:
+        a["ws_bytes"] = 1 << 40
+    a.update(case)
+    rc = L.qubo_bf_solve(a["Q"], a["n"], a["ldq"], a["dt"], a["k"], a["en"], a["masks"], a["status"], a["ws"],
+                         a["ws_bytes"], a["stream"])
+    assert rc == code
+    assert L.qubo_last_error()
+
+
+def test_batched_rejects_before_any_hip_call():
+    L = _lib.lib()
+    assert L.qubo_bf_solve_batched(0, FAKE, 10, FAKE, 0, 1, FAKE, FAKE, FAKE, FAKE, 1 << 40, None) == -1
+    assert L.qubo_bf_solve_batched(4, FAKE, 41, FAKE, 0, 1, FAKE, FAKE, FAKE, FAKE, 1 << 40, None) == -1
+    assert L.qubo_bf_solve_batched(4, FAKE, 10, None, 0, 1, FAKE, FAKE, FAKE, FAKE, 1 << 40, None) == -1
+    assert L.qubo_bf_solve_batched(4, FAKE, 10, FAKE, 0, 1, FAKE, FAKE, FAKE, FAKE, 8, None) == -3
+
+
+def test_tuning_knobs_roundtrip():
+    L = _lib.lib()
+    old = L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS)
+    before = L.qubo_bf_workspace_size(40, 16, 0)
+    assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 16) == 0
+    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == 16
+    assert L.qubo_bf_workspace_size(40, 16, 0) > before
+    assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 0) == 0
+    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == old
+    assert L.qubo_bf_set_tuning(99, 1) == -1
