@@ -39,7 +39,7 @@ def cpu_baseline(Q, n, k):
 
     rng = np.random.default_rng(123)
     span = 1 << 22
-    count = 64  # 64 ranges of 2^22 masks = 2^28 states
+    count = 256  # 256 ranges of 2^22 masks = 2^30 states
     starts = rng.choice(1 << (n - 22), count, replace=False)
     t0 = time.perf_counter()
     for s in starts:
@@ -47,8 +47,104 @@ def cpu_baseline(Q, n, k):
     dt = time.perf_counter() - t0
     states = count * span
     return {"value": states / dt, "unit": "states/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{count} random prefix ranges of 2^22 masks (2^28 of the 2^40 states), "
+            "sample": f"{count} random prefix ranges of 2^22 masks (2^30 of the 2^40 states), "
                       f"natural-order float64 evaluation, {dt:.1f} s"}
+
+
+def _time(fn, reps):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def extra_batched(dev):
+    """Config 4: 4096 QUBOs, n uniform in [12, 28], k=1 -- one captured graph
+    replay vs one qubo_bf_solve call per instance on the same stream."""
+    import torch
+
+    from paper_2310_19373_amd import _lib, api, inputs
+
+    Q, ns = inputs.batched_4096()
+    states = float(sum(1 << int(n) for n in ns))
+    solver = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=True)
+    solver.load(Q, ns)
+    solver.run()
+    torch.cuda.synchronize()
+    solver.results()
+    _lib.prof_enable(True)
+    _lib.prof_collect("walk_topk")
+    t_batched = _time(solver.run, 5)
+    _lib.prof_enable(False)
+    wms, wn = _lib.prof_collect("walk_topk")
+    e_b = solver.energies.clone()
+    # plain: one full solve (its own launch sequence) per instance
+    L = _lib.lib()
+    Qs = [torch.from_numpy(np.ascontiguousarray(Q[b, :int(n), :int(n)])).to(dev) for b, n in enumerate(ns)]
+    ws_bytes = max(L.qubo_bf_workspace_size(int(n), 1, _lib.QUBO_F32) for n in ns)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    en = torch.empty((len(ns), 1), dtype=torch.float64, device=dev)
+    mk = torch.empty((len(ns), 1), dtype=torch.int64, device=dev)
+    st = torch.empty(len(ns), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def plain():
+        for b, n in enumerate(ns):
+            _lib.check(L.qubo_bf_solve(Qs[b].data_ptr(), int(n), int(n), _lib.QUBO_F32, 1, en[b].data_ptr(),
+                                       mk[b].data_ptr(), st[b:b + 1].data_ptr(), ws.data_ptr(), ws_bytes, stream))
+
+    plain()
+    t_plain = _time(plain, 2)
+    same = bool(torch.equal(en, e_b))
+    return {"workload": "4096 QUBOs, n uniform in [12,28] (seed 3), float32 N(0,1), k=1",
+            "states": states, "batched_ms": t_batched * 1e3, "batched_states_per_s": states / t_batched,
+            "walk_ms": wms / max(wn, 1), "plain_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched,
+            "identical_to_plain": same}
+
+
+def extra_logz(dev):
+    """Config 5: 256 QUBOs n=24 x beta in {0.5,1,4}: one batched logZ forward +
+    backward vs one forward + backward call per (instance, beta) pair."""
+    import torch
+
+    from paper_2310_19373_amd import _lib, api, inputs
+
+    Q, beta = inputs.logz_256x24()
+    Qt = torch.from_numpy(Q).to(dev)
+    bt = torch.from_numpy(beta).to(dev)
+    ns = torch.full((len(beta),), 24, dtype=torch.int32, device=dev)
+
+    def fwd_bwd(Qx, bx, nx):
+        Qr = Qx.detach().requires_grad_(True)
+        lz = api.LogZ.apply(Qr, bx, nx)
+        lz.backward(torch.ones_like(lz))
+        return lz, Qr.grad
+
+    fwd_bwd(Qt, bt, ns)
+    _lib.prof_enable(True)
+    for nm in ("walk_topk", "walk_exp", "walk_grad"):
+        _lib.prof_collect(nm)
+    t_batched = _time(lambda: fwd_bwd(Qt, bt, ns), 3)
+    _lib.prof_enable(False)
+    kern = {nm: _lib.prof_collect(nm) for nm in ("walk_topk", "walk_exp", "walk_grad")}
+    lz_b, g_b = fwd_bwd(Qt, bt, ns)
+    one = torch.full((1,), 24, dtype=torch.int32, device=dev)
+
+    def plain():
+        for p in range(len(beta)):
+            fwd_bwd(Qt[p:p + 1], bt[p:p + 1], one)
+
+    plain()
+    t_plain = _time(plain, 1)
+    states = float(len(beta)) * (1 << 24)
+    return {"workload": "768 (instance, beta) pairs: 256 QUBOs n=24 float32 N(0,1/n) (seed 4) x beta {0.5,1,4}",
+            "states_per_pass": states, "batched_fwd_bwd_ms": t_batched * 1e3,
+            "walk_ms": {nm: ms / max(c, 1) for nm, (ms, c) in kern.items()},
+            "plain_fwd_bwd_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched}
 
 
 def main():
@@ -58,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (counter calibration for HBM bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the enumeration shards by prefix "
@@ -70,6 +168,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
     Q, xstar = inputs.single_n40_f32_planted()
     n, k = 40, 16
     Qd = torch.from_numpy(Q).to(dev)
@@ -130,6 +237,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, n, k)
+    if args.extra:
+        out["extra"] = {"batched": extra_batched(dev), "logz": extra_logz(dev)}
     print(json.dumps(out), flush=True)
 
 

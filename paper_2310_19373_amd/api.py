@@ -203,8 +203,85 @@ def masks_to_bits(masks, n: int) -> np.ndarray:
     return ((m[..., None] >> np.arange(n, dtype=np.uint64)) & np.uint64(1)).astype(np.uint8)
 
 
-def logz(Q, beta):
-    raise NotImplementedError("log-partition entry points are not built yet")
+def _logz_ws(batch, nmax, device):
+    L = _lib.lib()
+    nbytes = L.qubo_logz_workspace_size(batch, nmax)
+    if nbytes == 0:
+        raise ValueError(f"invalid arguments batch={batch}, nmax={nmax}: {_lib.last_error()}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
 
 
-LogZ = None
+class LogZ(torch.autograd.Function):
+    """logZ_b = log sum_x exp(-beta_b x^T Q_b x) with its exact gradient.
+
+    forward(Q [batch, nmax, nmax] float32, beta [batch] float32, ns [batch] int32)
+    -> logZ [batch] float64.  backward re-enumerates every state (adjoint walk)
+    and returns d/dQ (upper triangle incl. diagonal, zeros elsewhere) and d/dbeta.
+    """
+
+    @staticmethod
+    def forward(ctx, Q, beta, ns):
+        dev = Q.device
+        batch, nmax = Q.shape[0], Q.shape[1]
+        Qc = Q.detach().contiguous()
+        bc = beta.detach().to(torch.float32).contiguous()
+        nsc = ns.to(torch.int32).contiguous()
+        out = torch.empty(batch, dtype=torch.float64, device=dev)
+        status = torch.empty(batch, dtype=torch.int32, device=dev)
+        ws, nbytes = _logz_ws(batch, nmax, dev)
+        with torch.cuda.device(dev):
+            _lib.check(_lib.lib().qubo_logz_fwd(batch, Qc.data_ptr(), nmax, nsc.data_ptr(), bc.data_ptr(),
+                                                out.data_ptr(), status.data_ptr(), ws.data_ptr(), nbytes,
+                                                _stream(dev)))
+        _raise_status(status)
+        ctx.save_for_backward(Qc, bc, nsc, out)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        Qc, bc, nsc, lz = ctx.saved_tensors
+        dev = Qc.device
+        batch, nmax = Qc.shape[0], Qc.shape[1]
+        gq = torch.empty_like(Qc)
+        gb = torch.empty(batch, dtype=torch.float32, device=dev)
+        status = torch.empty(batch, dtype=torch.int32, device=dev)
+        gl = g.detach().to(torch.float32).contiguous()
+        ws, nbytes = _logz_ws(batch, nmax, dev)
+        with torch.cuda.device(dev):
+            _lib.check(_lib.lib().qubo_logz_bwd(batch, Qc.data_ptr(), nmax, nsc.data_ptr(), bc.data_ptr(),
+                                                lz.data_ptr(), gl.data_ptr(), gq.data_ptr(), gb.data_ptr(),
+                                                status.data_ptr(), ws.data_ptr(), nbytes, _stream(dev)))
+        _raise_status(status)
+        return gq, gb, None
+
+
+def logz(Q, beta, ns=None):
+    """Exact log-partition function log sum_x exp(-beta f_Q(x)), differentiable.
+
+    Q: (n, n) or (batch, nmax, nmax) float32 tensor (CUDA or CPU, upper
+    triangular); beta: float or (batch,) tensor; ns: instance sizes for a
+    padded batch (default: all nmax).  Returns float64: a 0-d tensor for a
+    single Q, else (batch,).
+    """
+    single = False
+    if not isinstance(Q, torch.Tensor):
+        Q = torch.as_tensor(np.asarray(Q))
+    if Q.ndim == 2:
+        Q = Q.unsqueeze(0)
+        single = True
+    if Q.dtype != torch.float32:
+        raise TypeError("Q must be float32")
+    if not Q.is_cuda:
+        Q = Q.to("cuda")
+    dev = Q.device
+    batch, nmax = Q.shape[0], Q.shape[1]
+    if not isinstance(beta, torch.Tensor):
+        beta = torch.full((batch,), float(beta), dtype=torch.float32, device=dev)
+    beta = beta.to(dev)
+    if beta.ndim == 0:
+        beta = beta.expand(batch)
+    if ns is None:
+        ns = torch.full((batch,), nmax, dtype=torch.int32, device=dev)
+    ns = _as_device(ns, torch.int32, dev)
+    out = LogZ.apply(Q, beta, ns)
+    return out[0] if single else out

@@ -27,6 +27,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # wave-level scans for the work-queue atomics use DPP, not a per-lane loop
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

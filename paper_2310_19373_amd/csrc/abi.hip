@@ -43,7 +43,7 @@ struct Tuning {
   int single_outer = 12;
   int single_unit = 12;
   int batched_outer = 8;
-  int waves_per_cu = 8;
+  int waves_per_cu = 12;
   int kprime = 0;
 };
 
@@ -221,6 +221,19 @@ PlanParams batched_params(int kp) {
   return pp;
 }
 
+PlanParams grad_params() {
+  PlanParams pp;
+  pp.no_max = 8;
+  pp.ub_min = 0;
+  pp.inner = 5;
+  pp.kprime = 1;
+  pp.waves = kMaxGridWaves;
+  pp.lane_bits = 6;
+  return pp;
+}
+
+int logz_npairs(int nmax) { return nmax * (nmax + 1) / 2; }
+
 bool valid_dtype(qubo_dtype dt) { return dt == QUBO_F32 || dt == QUBO_I32; }
 
 int check_k(int k, bool is_int) {
@@ -372,24 +385,70 @@ int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns,
 }
 
 size_t qubo_logz_workspace_size(int batch, int nmax) {
-  (void)batch;
-  (void)nmax;
-  return 0;
+  if (batch < 1 || nmax < 1 || nmax > 32) return 0;
+  const size_t f = make_layout(batch, nmax, batched_params(1), 1, 0).total;
+  const size_t g = make_layout(batch, nmax, grad_params(), logz_npairs(nmax), 0).total;
+  return f > g ? f : g;
 }
 
 int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, double* logz,
                   int32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
-  (void)batch; (void)Q; (void)nmax; (void)ns; (void)beta; (void)logz; (void)status; (void)ws; (void)ws_bytes;
-  (void)hip_stream;
-  return fail(QUBO_ERR_INVALID_ARG, "qubo_logz_fwd: not available in this build");
+  if (!Q || !ns || !beta || !logz || !status || !ws) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (batch < 1) return fail(QUBO_ERR_INVALID_ARG, "batch=%d < 1", batch);
+  if (nmax < 1 || nmax > 32) return fail(QUBO_ERR_INVALID_ARG, "nmax=%d outside [1, 32]", nmax);
+  const size_t need = qubo_logz_workspace_size(batch, nmax);
+  if (ws_bytes < need) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+  PlanParams pp = batched_params(1);
+  const Layout L = make_layout(batch, nmax, pp, 1, 0);
+  const Views v = make_views(ws, L, batch, nmax);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int waves = grid_waves();
+  pp.waves = waves;
+  const SplitH sh = split_host(nmax, pp);
+  const int64_t steps_bound = (int64_t)batch << sh.no;
+  HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
+  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
+  HIPCHK(launch_prep_tables(v, false, kInner, (int)(steps_bound < 4096 ? steps_bound : 4096), s));
+  {
+    ProfScope ps("walk_topk", s);  // minimum pass: E_ref per instance
+    HIPCHK(launch_walk_topk(v, false, waves, s));
+  }
+  HIPCHK(launch_reset_queue(v, s));
+  {
+    ProfScope ps("walk_exp", s);
+    HIPCHK(launch_walk_exp(v, beta, nullptr, waves, s));
+  }
+  HIPCHK(launch_finalize_logz(v, beta, nullptr, logz, status, s));
+  return QUBO_OK;
 }
 
 int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, const double* logz,
                   const float* grad_logz, float* grad_Q, float* grad_beta, int32_t* status, void* ws,
                   size_t ws_bytes, void* hip_stream) {
-  (void)batch; (void)Q; (void)nmax; (void)ns; (void)beta; (void)logz; (void)grad_logz; (void)grad_Q;
-  (void)grad_beta; (void)status; (void)ws; (void)ws_bytes; (void)hip_stream;
-  return fail(QUBO_ERR_INVALID_ARG, "qubo_logz_bwd: not available in this build");
+  if (!Q || !ns || !beta || !logz || !grad_logz || !grad_Q || !status || !ws)
+    return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (batch < 1) return fail(QUBO_ERR_INVALID_ARG, "batch=%d < 1", batch);
+  if (nmax < 1 || nmax > 32) return fail(QUBO_ERR_INVALID_ARG, "nmax=%d outside [1, 32]", nmax);
+  const size_t need = qubo_logz_workspace_size(batch, nmax);
+  if (ws_bytes < need) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+  PlanParams pp = grad_params();
+  const int np = logz_npairs(nmax);
+  const Layout L = make_layout(batch, nmax, pp, np, 0);
+  const Views v = make_views(ws, L, batch, nmax);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int waves = grid_waves();
+  pp.waves = waves;
+  const SplitH sh = split_host(nmax, pp);
+  const int64_t steps_bound = (int64_t)batch << sh.no;
+  HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
+  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, pp.inner, s));
+  HIPCHK(launch_prep_tables(v, false, pp.inner, (int)(steps_bound < 4096 ? steps_bound : 4096), s));
+  {
+    ProfScope ps("walk_grad", s);
+    HIPCHK(launch_walk_grad(v, beta, logz, waves, np, s));
+  }
+  HIPCHK(launch_finalize_grad(v, Q, beta, grad_logz, grad_Q, grad_beta, status, np, s));
+  return QUBO_OK;
 }
 
 }  // extern "C"

@@ -36,6 +36,8 @@ struct PlanParams {
 // instance of size n_single.  beta (may be null): instance sign = sign(beta).
 hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta,
                        const PlanParams& pp, hipStream_t s);
+// rewind the persistent work queue (between two walks over one plan)
+hipError_t launch_reset_queue(const Views& v, hipStream_t s);
 // prep: symmetric Q, sums, E_I table, float/int validation.
 hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
                             int inner, hipStream_t s);

@@ -111,6 +111,10 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
   }
 }
 
+// Rewinds the persistent work queue so a second walk can run over the same
+// plan (written by a kernel, not a memset, to stay graph-capture friendly).
+__global__ void reset_queue_kernel(Views v) { v.hdr->unit_counter = 0; }
+
 template <class T>
 __device__ double absd(T x) {
   return fabs((double)x);
@@ -248,6 +252,11 @@ __global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
 hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta, const PlanParams& pp,
                        hipStream_t s) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, v, ns, n_single, beta, pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(const Views& v, hipStream_t s) {
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, v);
   return hipGetLastError();
 }
 

@@ -24,95 +24,18 @@
 // threshold, an a-priori bound).  Every threshold is backed by K' real states,
 // so discarded states cannot enter the final top-K' (float: up to the bound
 // eps on the float32 rounding of e_j, which the certificate accounts for).
-#include <type_traits>
-
-#include "common.hpp"
-#include "launch.hpp"
-#include "wave.hpp"
+#include "walk.hpp"
 
 namespace qbf {
 
 namespace {
-
-template <class E>
-struct Ar;
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-
-template <>
-struct Ar<float> {
-  using W = double;
-  using V = f32x4;
-  __device__ static float inv() { return __builtin_inff(); }
-  __device__ static float mn(float a, float b) { return __builtin_fminf(a, b); }
-};
-template <>
-struct Ar<int32_t> {
-  using W = int64_t;
-  using V = i32x4;
-  __device__ static int32_t inv() { return kIntInvalid; }
-  __device__ static int32_t mn(int32_t a, int32_t b) { return a < b ? a : b; }
-};
-
-// acc = min(acc, C'(16K+Q) + T'(16K+Q)) over Q = 0..15 for register K of the
-// row-replicated T' table.
-template <int K, int Q, class E>
-__device__ __forceinline__ void block_min(E& acc, E t, const E* C) {
-  const E e0 = row_bcast<Q>(t) + C[16 * K + Q];
-  const E e1 = row_bcast<Q + 1>(t) + C[16 * K + Q + 1];
-  acc = Ar<E>::mn(Ar<E>::mn(acc, e0), e1);
-  if constexpr (Q + 2 < 16) block_min<K, Q + 2>(acc, t, C);
-}
-
-__device__ __forceinline__ int find_unit(const Views& v, uint64_t u) {
-  const gptr<const Inst> inst = gp((const Inst*)v.inst);
-  int lo = 0, hi = v.batch;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((uint64_t)inst[mid].unit_begin <= u) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// Instance fields as provably uniform (SGPR) values: the kernel's own atomics
-// keep the compiler from proving the loads unclobbered, so force uniformity.
-struct InstU {
-  int n, B, L, no, kp, status;
-  int64_t unit_begin, tab_off, slot_off, slot_cap;
-  double big;
-};
-
-__device__ __forceinline__ InstU load_inst(const Views& v, int b) {
-  const gptr<const Inst> I = gp((const Inst*)v.inst) + b;
-  InstU r;
-  r.n = uniform_i32(I->n);
-  r.B = uniform_i32(I->B);
-  r.L = uniform_i32(I->L);
-  r.no = uniform_i32(I->no);
-  r.kp = uniform_i32(I->kprime);
-  r.status = uniform_i32(I->status);
-  r.unit_begin = (int64_t)uniform_u64((uint64_t)I->unit_begin);
-  r.tab_off = (int64_t)uniform_u64((uint64_t)I->tab_off);
-  r.slot_off = (int64_t)uniform_u64((uint64_t)I->slot_off);
-  r.slot_cap = (int64_t)uniform_u64((uint64_t)I->slot_cap);
-  r.big = uniform_f64(I->big);
-  return r;
-}
-
-__device__ __forceinline__ double load_gthr(const Views& v, int b) {
-  const uint64_t g = __hip_atomic_load(gp(v.gthr) + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return dec_key(uniform_u64(g));
-}
 
 // Writes the wave's list to the next free slot of instance b.  A count above
 // the slot capacity is reported by the finalize kernel (it cannot happen: a
 // wave flushes an instance at most once per contiguous run of its units).
 __device__ void flush(const Views& v, int b, double lkey, uint64_t lmask, int lane) {
   const InstU I = load_inst(v, b);
-  uint32_t slot = 0;
-  if (lane == 0) slot = atomicAdd(v.flushcnt + b, 1u);
-  slot = readlane_u32(slot, 0);
+  const uint32_t slot = (uint32_t)uniform_i32((int)atomicAdd(v.flushcnt + b, lane == 0 ? 1u : 0u));
   if ((int64_t)slot < I.slot_cap && lane < I.kp) {
     const gptr<Slot> d = gp(v.slots) + (I.slot_off + slot) * I.kp + lane;
     d->key = lkey;
@@ -182,130 +105,146 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
                                           uint64_t& lmask, uint64_t& pub, typename Ar<E>::W* myc, int lane) {
   using W = typename Ar<E>::W;
   using V = typename Ar<E>::V;
-  const int pos0 = I.B + I.no;
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
-  const int64_t nm = v.nmax;
-  const gptr<const W> qs = gp((const W*)v.qs) + (int64_t)b * nm * nm;
-  const gptr<const W> ei = gp((const W*)v.ei) + (int64_t)b * 64;
 
-  // ---- lane init: prefix energy, inner cross fields, outer cross fields
-  W EP = 0;
-  W cI[6] = {0, 0, 0, 0, 0, 0};
-  for (int a = pos0; a < I.n; ++a) {
-    if (!((p >> (a - pos0)) & 1)) continue;
-    W row = qs[(int64_t)a * nm + a];
-    for (int c = a + 1; c < I.n; ++c)
-      if ((p >> (c - pos0)) & 1) row += qs[(int64_t)a * nm + c];
-    EP += row;
-#pragma unroll
-    for (int u = 0; u < 6; ++u)
-      if (u < I.B) cI[u] += qs[(int64_t)u * nm + a];
-  }
-  for (int l = 0; l < I.no; ++l) {
-    W c = 0;
-    for (int a = pos0; a < I.n; ++a)
-      if ((p >> (a - pos0)) & 1) c += qs[(int64_t)(I.B + l) * nm + a];
-    myc[l * kWave + lane] = c;
-  }
+  // ---- lane init: prefix energy, inner table, outer cross fields
   E C[kInnerStates];
-#pragma unroll
-  for (int j = 0; j < kInnerStates; ++j) {
-    W cj = ei[j];
-#pragma unroll
-    for (int u = 0; u < 6; ++u)
-      if ((j >> u) & 1) cj += cI[u];
-    C[j] = (valid && j < (1 << I.B)) ? (E)cj : Ar<E>::inv();
-  }
+  const W EP = lane_init<E, kInnerStates>(v, b, I, p, valid, myc, lane, C);
 
+  // ---- outer walk
+  // Dp = thr - E_P - X_PO(p, g(t)) is kept instead of the running value itself:
+  // the filter of step t is  min_j e_j <= Dp - E_O(g(t)).  A threshold change by
+  // delta moves Dp by delta.
+  using Acc = std::conditional_t<std::is_same_v<E, float>, double, int32_t>;
   double thr = fmin(fmin(load_gthr(v, b), I.big), readlane_f64(lkey, I.kp - 1));
+  Acc Dp = std::is_same_v<E, float> ? (Acc)(thr - (double)EP) : (Acc)((int32_t)thr - (int32_t)EP);
   const uint32_t steps = 1u << I.no;
-  const int q = lane & 15;
-  const gptr<const V> trow = (gptr<const V>)(gp((const E*)v.tab) + I.tab_off * kInnerStates) + q;
+  // T' rows through a buffer resource: per-lane byte offset in a VGPR (fixed),
+  // per-step row offset in an SGPR, no address arithmetic on the VALU; reads
+  // past the instance's rows return zeros.
+  const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(gp((const E*)v.tab) + I.tab_off * kInnerStates), (short)0,
+      (int)(steps * (uint32_t)(kInnerStates * sizeof(E))), 0x00020000);
+  const int qoff = (lane & 15) * 16;
   const gptr<const StepRec> rec = gp((const StepRec*)v.rec) + I.tab_off;
-  // Operands of step t, loaded one step ahead: T' row, E_O (or -E_O), and the
-  // cross field c_l of the bit flipped into step t.  Indices are clamped so the
-  // loads are unconditional (the clamped values are never used).
+  const W c0 = I.no > 0 ? myc[lane] : (W)0;
+  const W c1 = I.no > 1 ? myc[kWave + lane] : (W)0;
+  const W c2 = I.no > 2 ? myc[2 * kWave + lane] : (W)0;
+
+  // Operands of a step (T' row in the row-broadcast layout, E_O term), loaded
+  // one step ahead; the index is clamped so loads are unconditional.
   struct Ops {
     V tv;
-    double eo;
-    int32_t neo;
-    W c;
+    Acc eo;  // +E_O (float path) or -E_O (int path)
   };
   auto load = [&](uint32_t t) {
     const uint32_t tt = t < steps ? t : steps - 1;
     Ops o;
-    o.tv = trow[tt * 16];
+    o.tv = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(
+                                     trs, qoff, (int)(tt * (uint32_t)(kInnerStates * sizeof(E))), 0));
     if constexpr (std::is_same_v<E, float>) o.eo = rec[tt].eo;
-    else o.neo = rec[tt].neo;
-    o.c = myc[(tt ? __builtin_ctz(tt) : 0) * kWave + lane];
+    else o.eo = rec[tt].neo;
     return o;
   };
-
-  if constexpr (std::is_same_v<E, float>) {
-    double K = EP;  // E_P + X_PO(p, g(t))
-    // One outer step: flip, block minimum over the 64 inner states, filter.
-    auto step = [&](uint32_t t, const Ops& o) {
-      if (t != 0) {
-        const double sg = ((t >> (__builtin_ctz(t) + 1)) & 1) ? -1.0 : 1.0;
-        K = __builtin_fma(sg, o.c, K);
-      }
-      const double KE = K + o.eo;
-      const double D = thr - KE;
-      float acc = __builtin_inff();
-      block_min<0, 0>(acc, o.tv.x, C);
-      block_min<1, 0>(acc, o.tv.y, C);
-      block_min<2, 0>(acc, o.tv.z, C);
-      block_min<3, 0>(acc, o.tv.w, C);
-      if (__builtin_expect(ballot((double)acc <= D) != 0, 0))
-        replay<E>(v, b, I, t, p, valid, KE, thr, lkey, lmask, pub, lane);
-      if ((t & 63) == 63) thr = fmin(thr, load_gthr(v, b));
-    };
-    Ops oa = load(0);
-    for (uint32_t t = 0; t < steps; t += 2) {
-      // steps is 1 or even; the two operand buffers alternate
-      const Ops ob = load(t + 1);
-      step(t, oa);
-      if (t + 1 >= steps) break;
-      oa = load(t + 2);
-      step(t + 1, ob);
+  // Threshold refresh: fold an improvement of thr into Dp.
+  auto retune = [&](double nthr) {
+    if constexpr (std::is_same_v<E, float>) {
+      Dp += nthr - thr;
+    } else {
+      Dp += (int32_t)nthr - (int32_t)thr;
     }
-  } else {
-    int32_t NK = -(int32_t)EP;  // -(E_P + X_PO(p, g(t)))
-    int32_t thr_i = (int32_t)thr;
-    auto step = [&](uint32_t t, const Ops& o) {
-      if (t != 0) {
-        const int32_t c = (int32_t)o.c;
-        NK = ((t >> (__builtin_ctz(t) + 1)) & 1) ? NK + c : NK - c;
-      }
-      const int32_t D = thr_i + NK + o.neo;
-      int32_t acc = kIntInvalid;
-      block_min<0, 0>(acc, o.tv.x, C);
-      block_min<1, 0>(acc, o.tv.y, C);
-      block_min<2, 0>(acc, o.tv.z, C);
-      block_min<3, 0>(acc, o.tv.w, C);
-      if (__builtin_expect(ballot(acc <= D) != 0, 0)) {
-        replay<E>(v, b, I, t, p, valid, -(int64_t)NK - (int64_t)o.neo, thr, lkey, lmask, pub, lane);
-        thr_i = (int32_t)thr;
-      }
-      if ((t & 63) == 63) {
-        thr = fmin(thr, load_gthr(v, b));
-        thr_i = (int32_t)thr;
-      }
-    };
-    Ops oa = load(0);
-    for (uint32_t t = 0; t < steps; t += 2) {
-      const Ops ob = load(t + 1);
-      step(t, oa);
-      if (t + 1 >= steps) break;
-      oa = load(t + 2);
-      step(t + 1, ob);
+    thr = nthr;
+  };
+  // Block minimum over the 64 inner states of step t and the filter.
+  auto body = [&](uint32_t t, const Ops& o) {
+    E acc = Ar<E>::inv();
+    block_min<0, 0>(acc, o.tv.x, C);
+    block_min<1, 0>(acc, o.tv.y, C);
+    block_min<2, 0>(acc, o.tv.z, C);
+    block_min<3, 0>(acc, o.tv.w, C);
+    bool hit;
+    if constexpr (std::is_same_v<E, float>) hit = (double)acc <= Dp - o.eo;
+    else hit = acc <= Dp + o.eo;
+    if (__builtin_expect(ballot(hit) != 0, 0)) {
+      double nthr = thr;
+      W KE;
+      if constexpr (std::is_same_v<E, float>) KE = thr - Dp + o.eo;
+      else KE = (int64_t)(int32_t)thr - (int64_t)Dp - (int64_t)o.eo;
+      replay<E>(v, b, I, t, p, valid, KE, nthr, lkey, lmask, pub, lane);
+      retune(nthr);
+    }
+  };
+  // Flip of a bit into step t: it turns on (Dp -= c) or off (Dp += c).
+  auto flip_on = [&](W c) { Dp -= (Acc)c; };
+  auto flip_off = [&](W c) { Dp += (Acc)c; };
+  auto flip_sign = [&](bool off, W c) {  // sign known only at run time (uniform)
+    if constexpr (std::is_same_v<E, float>) {
+      Dp = __builtin_fma(off ? 1.0 : -1.0, c, Dp);
+    } else {
+      if (off) flip_off(c);
+      else flip_on(c);
+    }
+  };
+  auto flip = [&](uint32_t t) {  // general flip: bit CTZ(t), off iff bit CTZ(t)+1 of t is set
+    const int l = __builtin_ctz(t);
+    flip_sign((t >> (l + 1)) & 1, myc[l * kWave + lane]);
+  };
+
+  if (steps < 16) {
+    // short walks (small instances): one step at a time
+    Ops o = load(0);
+    for (uint32_t t = 0; t < steps; ++t) {
+      const Ops on = load(t + 1);
+      if (t) flip(t);
+      body(t, o);
+      o = on;
+    }
+    return;
+  }
+  // steps >= 16: unrolled by 8.  Within group q (t = 8q .. 8q+8) bit 0 flips
+  // on at 8q+1 and 8q+5 and off at 8q+3 and 8q+7, bit 1 on at 8q+2 and off at
+  // 8q+6, bit 2 at 8q+4 (off for odd q), bit 3+CTZ(q+1) at 8q+8.
+  Ops ev = load(0), od = load(1);
+  body(0, ev);
+  ev = load(2);
+  const uint32_t groups = steps >> 3;
+  for (uint32_t q = 0;; ++q) {
+    const uint32_t t = 8 * q;
+    flip_on(c0);
+    body(t + 1, od);
+    od = load(t + 3);
+    flip_on(c1);
+    body(t + 2, ev);
+    ev = load(t + 4);
+    flip_off(c0);
+    body(t + 3, od);
+    od = load(t + 5);
+    flip_sign(q & 1, c2);
+    body(t + 4, ev);
+    ev = load(t + 6);
+    flip_on(c0);
+    body(t + 5, od);
+    od = load(t + 7);
+    flip_off(c1);
+    body(t + 6, ev);
+    ev = load(t + 8);
+    flip_off(c0);
+    body(t + 7, od);
+    od = load(t + 9);
+    if (q + 1 == groups) break;
+    flip(t + 8);
+    body(t + 8, ev);
+    ev = load(t + 10);
+    if (((q + 1) & 7) == 0) {
+      const double g = load_gthr(v, b);
+      if (g < thr) retune(g);
     }
   }
 }
 
 template <class E>
-__global__ void __launch_bounds__(kBlock) walk_topk_kernel(Views v) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_kernel(Views v) {
   using W = typename Ar<E>::W;
   __shared__ W ctab[kWavesPerBlock][kMaxOuter * kWave];
   const int lane = threadIdx.x & 63;
@@ -316,9 +255,7 @@ __global__ void __launch_bounds__(kBlock) walk_topk_kernel(Views v) {
   uint64_t pub = ~0ull;
   int cur = -1;
   for (;;) {
-    uint64_t u = 0;
-    if (lane == 0) u = atomicAdd((unsigned long long*)&v.hdr->unit_counter, 1ull);
-    u = readlane_u64(u, 0);
+    const uint64_t u = next_unit(v, lane);
     if (u >= total_units) break;
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     if (b != cur) {
