@@ -148,6 +148,9 @@ const char* qubo_version(void);
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
  *   QUBO_TUNE_KPRIME              candidate list length override (float path;
  *                                 values below k make the certificate fail)
+ *   QUBO_TUNE_CHUNK_SINGLE        work units per queue pull, single solve
+ *   QUBO_TUNE_CHUNK_BATCHED       work units per queue pull, batched / logZ
+ *   QUBO_TUNE_DYNAMIC_QUEUE       1: atomic work queue; -1: static assignment
  * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)
  * set the initial values.  Returns QUBO_OK or QUBO_ERR_INVALID_ARG.
  */
@@ -156,7 +159,10 @@ enum {
   QUBO_TUNE_SINGLE_UNIT_BITS = 2,
   QUBO_TUNE_BATCHED_OUTER_BITS = 3,
   QUBO_TUNE_WAVES_PER_CU = 4,
-  QUBO_TUNE_KPRIME = 5
+  QUBO_TUNE_KPRIME = 5,
+  QUBO_TUNE_CHUNK_SINGLE = 6,
+  QUBO_TUNE_CHUNK_BATCHED = 7,
+  QUBO_TUNE_DYNAMIC_QUEUE = 8
 };
 int qubo_bf_set_tuning(int knob, int value);
 int qubo_bf_get_tuning(int knob);

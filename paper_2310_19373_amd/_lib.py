@@ -29,6 +29,9 @@ TUNE_SINGLE_UNIT_BITS = 2
 TUNE_BATCHED_OUTER_BITS = 3
 TUNE_WAVES_PER_CU = 4
 TUNE_KPRIME = 5
+TUNE_CHUNK_SINGLE = 6
+TUNE_CHUNK_BATCHED = 7
+TUNE_DYNAMIC_QUEUE = 8
 
 # Every symbol include/qubo_bf.h declares: name -> (restype, argtypes)
 _vp, _sz, _i, _i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64

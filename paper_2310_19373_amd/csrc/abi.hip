@@ -45,6 +45,9 @@ struct Tuning {
   int batched_outer = 8;
   int waves_per_cu = 12;
   int kprime = 0;
+  int chunk_single = 4;
+  int chunk_batched = 8;
+  int dyn = 1;
 };
 
 int env_int(const char* name, int dflt) {
@@ -61,6 +64,9 @@ Tuning& tuning() {
     d.batched_outer = env_int("QUBO_BF_BATCHED_OUTER_BITS", d.batched_outer);
     d.waves_per_cu = env_int("QUBO_BF_WAVES_PER_CU", d.waves_per_cu);
     d.kprime = env_int("QUBO_BF_KPRIME", d.kprime);
+    d.chunk_single = env_int("QUBO_BF_CHUNK_SINGLE", d.chunk_single);
+    d.chunk_batched = env_int("QUBO_BF_CHUNK_BATCHED", d.chunk_batched);
+    d.dyn = env_int("QUBO_BF_DYNAMIC_QUEUE", d.dyn);
     return d;
   }();
   return t;
@@ -143,8 +149,11 @@ SplitH split_host(int n, const PlanParams& pp) {
 }
 
 struct Layout {
-  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, slots, part, total;
+  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, slots, part, lt, umap, total;
+  int64_t umap_cap;
 };
+
+constexpr int64_t kUnitMapMax = int64_t(1) << 24;  // unit -> instance map entries
 
 // Worst case over n <= nmax (steps and units grow with n).
 Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_unit, int64_t part_per_inst) {
@@ -175,6 +184,11 @@ Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_u
   o += al(sizeof(Slot) * (size_t)batch * slots * pp.kprime);
   L.part = o;
   o += al(8 * (size_t)batch * (units * part_per_unit + part_per_inst));
+  L.lt = o;
+  o += al(8 * (size_t)batch * 64 * kLaneRec);
+  L.umap = o;
+  L.umap_cap = (batch > 1 && (int64_t)batch * units <= kUnitMapMax) ? (int64_t)batch * units : 0;
+  o += al(4 * (size_t)L.umap_cap);
   L.total = o;
   return L;
 }
@@ -192,8 +206,13 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.rec = (StepRec*)(p + L.rec);
   v.slots = (Slot*)(p + L.slots);
   v.part = (double*)(p + L.part);
+  v.lt = p + L.lt;
+  v.umap = L.umap_cap > 0 ? (uint32_t*)(p + L.umap) : nullptr;
+  v.umap_cap = L.umap_cap;
   v.batch = batch;
   v.nmax = nmax;
+  v.chunk = clampi(batch > 1 ? tuning().chunk_batched : tuning().chunk_single, 1, 1 << 20);
+  v.dyn = tuning().dyn != 0;
   return v;
 }
 
@@ -255,6 +274,7 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   pp.waves = waves;
   HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
   HIPCHK(launch_prep_inst(v, Q, ldq, stride, is_int, kInner, s));
+  HIPCHK(launch_prep_lanes(v, is_int, s));
   int tw = (int)(steps_hint < 4096 ? steps_hint : 4096);
   HIPCHK(launch_prep_tables(v, is_int, kInner, tw < 4 ? 4 : tw, s));
   {
@@ -282,6 +302,9 @@ int qubo_bf_set_tuning(int knob, int value) {
     case QUBO_TUNE_BATCHED_OUTER_BITS: t.batched_outer = value > 0 ? clampi(value, 0, kMaxOuter) : d.batched_outer; break;
     case QUBO_TUNE_WAVES_PER_CU: t.waves_per_cu = value > 0 ? clampi(value, 1, 32) : d.waves_per_cu; break;
     case QUBO_TUNE_KPRIME: t.kprime = value > 0 ? clampi(value, 1, kMaxKPrime) : 0; break;
+    case QUBO_TUNE_CHUNK_SINGLE: t.chunk_single = value > 0 ? value : d.chunk_single; break;
+    case QUBO_TUNE_CHUNK_BATCHED: t.chunk_batched = value > 0 ? value : d.chunk_batched; break;
+    case QUBO_TUNE_DYNAMIC_QUEUE: t.dyn = value > 0 ? 1 : (value < 0 ? 0 : d.dyn); break;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
   return QUBO_OK;
@@ -295,6 +318,9 @@ int qubo_bf_get_tuning(int knob) {
     case QUBO_TUNE_BATCHED_OUTER_BITS: return t.batched_outer;
     case QUBO_TUNE_WAVES_PER_CU: return t.waves_per_cu;
     case QUBO_TUNE_KPRIME: return t.kprime;
+    case QUBO_TUNE_CHUNK_SINGLE: return t.chunk_single;
+    case QUBO_TUNE_CHUNK_BATCHED: return t.chunk_batched;
+    case QUBO_TUNE_DYNAMIC_QUEUE: return t.dyn;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
 }
@@ -408,6 +434,7 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
+  HIPCHK(launch_prep_lanes(v, false, s));
   HIPCHK(launch_prep_tables(v, false, kInner, (int)(steps_bound < 4096 ? steps_bound : 4096), s));
   {
     ProfScope ps("walk_topk", s);  // minimum pass: E_ref per instance
@@ -442,6 +469,7 @@ int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, pp.inner, s));
+  HIPCHK(launch_prep_lanes(v, false, s));
   HIPCHK(launch_prep_tables(v, false, pp.inner, (int)(steps_bound < 4096 ? steps_bound : 4096), s));
   {
     ProfScope ps("walk_grad", s);

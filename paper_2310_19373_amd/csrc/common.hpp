@@ -29,7 +29,14 @@ namespace qbf {
 constexpr int kWave = 64;
 constexpr int kInner = 6;                 // inner bits of the top-k / logZ-forward walks
 constexpr int kInnerStates = 1 << kInner;  // 64 table entries per lane
-constexpr int kMaxOuter = 20;              // outer bits per unit (per-lane LDS table bound)
+constexpr int kMaxOuter = 14;              // outer bits per work unit (upper bound)
+// Per-wave LDS table of the walks, rows of 64 lane entries: rows [0, no) hold
+// the outer cross fields c_l, rows kCIRow.. the six inner cross fields, row
+// kTileRow the per-unit tile sums exchanged between lanes.
+constexpr int kCIRow = kMaxOuter;
+constexpr int kTileRow = kMaxOuter + 6;
+constexpr int kWaveRows = kMaxOuter + 8;
+constexpr int kLaneRec = 24;               // words per lane record of the lane table
 constexpr int kBlock = 256;                // threads per block of the walk kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxKPrime = 64;             // candidate list length (one entry per lane)

@@ -20,7 +20,12 @@ struct Views {
   StepRec* rec;    // [total_steps]
   Slot* slots;     // [total_slots][kprime]
   double* part;    // per-unit partial sums (logZ forward) / per-wave moments (gradient)
+  void* lt;        // [batch][64][kLaneRec] lane table (double or int64), see prep_lanes
+  uint32_t* umap;  // [umap_cap] work unit -> instance, or null (binary search)
+  int64_t umap_cap;
   int batch, nmax;
+  int chunk;       // consecutive work units per queue pull
+  int dyn;         // 1: atomic work queue, 0: static round-robin of chunks
 };
 
 struct PlanParams {
@@ -41,6 +46,9 @@ hipError_t launch_reset_queue(const Views& v, hipStream_t s);
 // prep: symmetric Q, sums, E_I table, float/int validation.
 hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
                             int inner, hipStream_t s);
+// per-instance lane table: contributions of the lane bits to E_P and to the
+// inner / outer cross fields, for each of the 64 lane values.
+hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s);
 // per-step tables of the outer walk.
 hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int grid_waves, hipStream_t s);
 // persistent top-k walk.

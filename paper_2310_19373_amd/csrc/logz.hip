@@ -59,13 +59,13 @@ __device__ __forceinline__ void block_exp(float (&acc)[4], float t, const float*
 }
 
 __global__ void __launch_bounds__(kBlock) walk_exp_kernel(Views v, const float* beta) {
-  __shared__ double ctab[kWavesPerBlock][kMaxOuter * kWave];
+  __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   double* myc = ctab[threadIdx.x >> 6];
   const uint64_t total_units = uniform_u64(gp((const Header*)v.hdr)->total_units);
-  for (;;) {
-    const uint64_t u = next_unit(v, lane);
-    if (u >= total_units) break;
+  WorkIter it(v, total_units);
+  uint64_t u;
+  while (it.next(v, lane, u)) {
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     const InstU I = load_inst(v, b);
     if (I.status != 0) {
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) walk_exp_kernel(Views v, const float* 
     const bool valid = lane < (1 << I.L);
     const uint64_t p = (local << I.L) | (uint64_t)lane;
     float C[kInnerStates];
-    const double EP = lane_init<float, kInnerStates>(v, b, I, p, valid, myc, lane, C);
+    const double EP = lane_init<float, kInnerStates>(v, b, I, local, valid, myc, lane, C);
     const double bb = fabs((double)gp(beta)[b]) * kLog2e;
     const double eref = load_gthr(v, b);
     // beta = 0: a tiny negative slope keeps invalid table entries (+inf) at
@@ -170,13 +170,13 @@ __device__ __forceinline__ int pidx(int n, int i, int j) { return i * n - (i * (
 
 __global__ void __launch_bounds__(kBlock) walk_grad_kernel(Views v, const float* beta, const double* logz,
                                                           int npairs) {
-  __shared__ double ctab[kWavesPerBlock][kGradMaxOuter * kWave];
+  __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   double* myc = ctab[threadIdx.x >> 6];
   const uint64_t total_units = uniform_u64(gp((const Header*)v.hdr)->total_units);
-  for (;;) {
-    const uint64_t u = next_unit(v, lane);
-    if (u >= total_units) break;
+  WorkIter it(v, total_units);
+  uint64_t u;
+  while (it.next(v, lane, u)) {
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     const InstU I = load_inst(v, b);
     const gptr<double> out = gp(v.part) + (int64_t)u * npairs;
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) walk_grad_kernel(Views v, const float*
     const bool valid = lane < (1 << I.L);
     const uint64_t p = (local << I.L) | (uint64_t)lane;
     float C[kGradStates];
-    const double EP = lane_init<float, kGradStates>(v, b, I, p, valid, myc, lane, C);
+    const double EP = lane_init<float, kGradStates>(v, b, I, local, valid, myc, lane, C);
     const double bb = fabs((double)gp(beta)[b]) * kLog2e;
     const double lz2 = uniform_f64(gp(logz)[b]) * kLog2e;
     const float nb = bb > 0.0 ? (float)-bb : -1e-30f;  // see walk_exp_kernel

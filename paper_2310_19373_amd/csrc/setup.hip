@@ -92,6 +92,9 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
       I.tab_off = cs;
       I.slot_off = csl;
       I.slot_cap = min<int64_t>(s.units, pp.waves);
+      if (v.umap)
+        for (int64_t u = 0; u < s.units; ++u)
+          if (cu + u < v.umap_cap) v.umap[cu + u] = (uint32_t)b;
       cu += s.units;
       cs += s.steps;
       csl += I.slot_cap;
@@ -192,6 +195,33 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
   }
 }
 
+// Lane table: for each lane value l (the L lane bits at positions B+no..),
+// record [0] = the lane bits' own energy, [1+u] = sum_{set lane bits a}
+// S(u, a) for inner bits u, [8+k] = sum_{set lane bits a} S(B+k, a) for outer
+// bits k.
+template <class W>
+__global__ void __launch_bounds__(64) prep_lanes_kernel(Views v) {
+  const int b = blockIdx.x, l = threadIdx.x;
+  const Inst* I = &v.inst[b];
+  W* lt = (W*)v.lt + ((int64_t)b * 64 + l) * kLaneRec;
+  W rec[kLaneRec];
+  for (int i = 0; i < kLaneRec; ++i) rec[i] = 0;
+  if (I->status == 0 && l < (1 << I->L)) {
+    const int B = I->B, no = I->no, pos0 = B + no, nm = v.nmax;
+    const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
+    for (int a = 0; a < I->L; ++a) {
+      if (!((l >> a) & 1)) continue;
+      const int ra = pos0 + a;
+      rec[0] += qs[(int64_t)ra * nm + ra];
+      for (int a2 = a + 1; a2 < I->L; ++a2)
+        if ((l >> a2) & 1) rec[0] += qs[(int64_t)ra * nm + pos0 + a2];
+      for (int u = 0; u < B && u < 6; ++u) rec[1 + u] += qs[(int64_t)u * nm + ra];
+      for (int k = 0; k < no && 8 + k < kLaneRec; ++k) rec[8 + k] += qs[(int64_t)(B + k) * nm + ra];
+    }
+  }
+  for (int i = 0; i < kLaneRec; ++i) lt[i] = rec[i];
+}
+
 __device__ int find_by_tab(const Views& v, int64_t s) {
   int lo = 0, hi = v.batch;
   while (hi - lo > 1) {
@@ -268,6 +298,14 @@ hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t 
   else
     hipLaunchKernelGGL((prep_inst_kernel<float, double>), dim3(v.batch), dim3(256), 0, s, v, (const float*)q,
                        ldq, stride, inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s) {
+  if (is_int)
+    hipLaunchKernelGGL(prep_lanes_kernel<int64_t>, dim3(v.batch), dim3(64), 0, s, v);
+  else
+    hipLaunchKernelGGL(prep_lanes_kernel<double>, dim3(v.batch), dim3(64), 0, s, v);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ __device__ __forceinline__ void block_min(E& acc, E t, const E* C) {
 }
 
 __device__ __forceinline__ int find_unit(const Views& v, uint64_t u) {
+  if (v.umap) return uniform_i32((int)gp((const uint32_t*)v.umap)[u]);
   const gptr<const Inst> inst = gp((const Inst*)v.inst);
   int lo = 0, hi = v.batch;
   while (hi - lo > 1) {
@@ -61,6 +62,39 @@ __device__ __forceinline__ uint64_t next_unit(const Views& v, int lane) {
   const uint64_t r = atomicAdd((unsigned long long*)&v.hdr->unit_counter, lane == 0 ? 1ull : 0ull);
   return uniform_u64(r);
 }
+
+// Work distribution of the persistent walks: chunks of v.chunk consecutive
+// units, taken from the atomic queue (v.dyn) or statically (wave w of G takes
+// chunks w, w+G, ...).  Consecutive units of a chunk mostly belong to one
+// instance, so a wave's candidate list carries over between them.
+struct WorkIter {
+  uint64_t total, chunk, u = 0, u_end = 0, next_static;
+  int64_t stride;
+  bool dyn;
+  __device__ WorkIter(const Views& v, uint64_t total_units) {
+    total = total_units;
+    chunk = (uint64_t)(v.chunk > 0 ? v.chunk : 1);
+    dyn = v.dyn != 0;
+    next_static = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    stride = (int64_t)gridDim.x * kWavesPerBlock;
+  }
+  __device__ __forceinline__ bool next(const Views& v, int lane, uint64_t& unit) {
+    if (u >= u_end) {
+      uint64_t c;
+      if (dyn) {
+        c = next_unit(v, lane);
+      } else {
+        c = next_static;
+        next_static += (uint64_t)stride;
+      }
+      u = c * chunk;
+      if (u >= total) return false;
+      u_end = u + chunk < total ? u + chunk : total;
+    }
+    unit = u++;
+    return true;
+  }
+};
 
 // Instance fields as provably uniform (SGPR) values: the kernel's own atomics
 // keep the compiler from proving the loads unclobbered, so force uniformity.
@@ -92,37 +126,65 @@ __device__ __forceinline__ double load_gthr(const Views& v, int b) {
   return dec_key(uniform_u64(g));
 }
 
-// Per-lane init of a work unit.  The lane owns the prefix p (lane and tile
-// bits, at positions B+no and up).  Returns E_P(p); fills the inner table
-// C'(j) = E_I(j) + X_PI(p, j) (invalid lanes and inner states get the type's
-// sentinel) and writes the cross fields c_l = sum_{v in prefix} S_{B+l, v} x_v
-// of the outer bits to the wave's LDS table (entry l*64 + lane).
+// Per-lane init of a work unit.  The lane owns the prefix p: its lane bits
+// (positions B+no ..) and the unit's tile bits (positions B+no+L ..).  Fills
+//   C'(j) = E_I(j) + X_PI(p, j)  for the 64 (NB) inner states (invalid lanes and
+//           inner states get the type's sentinel),
+//   LDS rows 0..no-1:   c_l = sum_{v in prefix} S_{B+l, v} x_v  (outer cross fields),
+//   LDS rows kCIRow+u:  cI_u = sum_{v in prefix} S_{u, v} x_v   (inner cross fields),
+// and returns E_P(p).  The lane-bit parts come from the instance's lane table;
+// the tile-bit parts are summed lane-parallel (lane t takes row t, lane t also
+// tile row t for E_tile) with independent loads, and exchanged through LDS.
 template <class E, int NB>
-__device__ __forceinline__ typename Ar<E>::W lane_init(const Views& v, int b, const InstU& I, uint64_t p, bool valid,
-                                                       typename Ar<E>::W* myc, int lane, E (&C)[NB]) {
+__device__ __forceinline__ typename Ar<E>::W lane_init(const Views& v, int b, const InstU& I, uint64_t local,
+                                                       bool valid, typename Ar<E>::W* myc, int lane, E (&C)[NB]) {
   using W = typename Ar<E>::W;
   const int pos0 = I.B + I.no;
+  const int tp0 = pos0 + I.L;  // first tile bit
+  const int tb = I.n - tp0;
   const int64_t nm = v.nmax;
   const gptr<const W> qs = gp((const W*)v.qs) + (int64_t)b * nm * nm;
   const gptr<const W> ei = gp((const W*)v.ei) + (int64_t)b * 64;
-  W EP = 0;
-  W cI[6] = {0, 0, 0, 0, 0, 0};
-  for (int a = pos0; a < I.n; ++a) {
-    if (!((p >> (a - pos0)) & 1)) continue;
-    W row = qs[(int64_t)a * nm + a];
-    for (int c = a + 1; c < I.n; ++c)
-      if ((p >> (c - pos0)) & 1) row += qs[(int64_t)a * nm + c];
-    EP += row;
+  // tile sums: S (lane t < tp0) = sum_{set tile bits k} S(t, tp0+k);
+  // R (tile row t = lane, bit t set) = sum_{set tile bits k >= t} Q(tp0+t, tp0+k)
+  W S = 0, R = 0;
+  const bool xt = lane < tb && ((local >> lane) & 1);
+  const int64_t srow = (int64_t)(lane < tp0 ? lane : 0) * nm;
+  const int64_t rrow = (int64_t)(tp0 + (lane < tb ? lane : 0)) * nm;
+  for (int k0 = 0; k0 < tb; k0 += 8) {
+    W s8[8], r8[8];
 #pragma unroll
-    for (int u = 0; u < 6; ++u)
-      if (u < I.B) cI[u] += qs[(int64_t)u * nm + a];
+    for (int d = 0; d < 8; ++d) {  // independent loads, clamped addresses
+      const int kc = k0 + d < tb ? k0 + d : tb - 1;
+      s8[d] = qs[srow + tp0 + kc];
+      r8[d] = qs[rrow + tp0 + kc];
+    }
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const int k = k0 + d;
+      const bool xk = k < tb && ((local >> k) & 1);
+      if (xk && lane < tp0) S += s8[d];
+      if (xk && xt && lane <= k) R += r8[d];
+    }
   }
-  for (int l = 0; l < I.no; ++l) {
-    W c = 0;
-    for (int a = pos0; a < I.n; ++a)
-      if ((p >> (a - pos0)) & 1) c += qs[(int64_t)(I.B + l) * nm + a];
-    myc[l * kWave + lane] = c;
+  W etile = R;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) etile += __shfl_xor(etile, o);
+  if constexpr (std::is_same_v<W, double>) etile = uniform_f64(etile);
+  else etile = (W)uniform_u64((uint64_t)etile);
+  myc[kTileRow * kWave + lane] = S;
+  // lane record + tile sums
+  const gptr<const W> lt = gp((const W*)v.lt) + ((int64_t)b * 64 + lane) * kLaneRec;
+  W EP = etile + lt[0];
+  for (int a = 0; a < I.L; ++a)
+    if ((lane >> a) & 1) EP += myc[kTileRow * kWave + pos0 + a];
+  W cI[6];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    cI[u] = u < I.B ? lt[1 + u] + myc[kTileRow * kWave + u] : (W)0;
+    myc[(kCIRow + u) * kWave + lane] = cI[u];
   }
+  for (int l = 0; l < I.no; ++l) myc[l * kWave + lane] = lt[8 + l] + myc[kTileRow * kWave + I.B + l];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     W cj = ei[j];

@@ -48,19 +48,13 @@ __device__ void flush(const Views& v, int b, double lkey, uint64_t lmask, int la
 template <class E>
 __device__ __forceinline__ void replay(const Views& v, int b, const InstU& I, uint32_t t, uint64_t p, bool valid,
                                        typename Ar<E>::W KE, double& thr, double& lkey, uint64_t& lmask,
-                                       uint64_t& pub, int lane) {
+                                       uint64_t& pub, const typename Ar<E>::W* myc, int lane) {
   using W = typename Ar<E>::W;
   const int pos0 = I.B + I.no;
-  const int64_t nm = v.nmax;
-  const gptr<const W> qs = gp((const W*)v.qs) + (int64_t)b * nm * nm;
   const gptr<const W> ei = gp((const W*)v.ei) + (int64_t)b * 64;
-  W cI[6] = {0, 0, 0, 0, 0, 0};
-  for (int a = pos0; a < I.n; ++a) {
-    if (!((p >> (a - pos0)) & 1)) continue;
+  W cI[6];
 #pragma unroll
-    for (int u = 0; u < 6; ++u)
-      if (u < I.B) cI[u] += qs[(int64_t)u * nm + a];
-  }
+  for (int u = 0; u < 6; ++u) cI[u] = myc[(kCIRow + u) * kWave + lane];  // written by lane_init
   const gptr<const StepRec> r = gp((const StepRec*)v.rec) + I.tab_off + t;
   W h[6];
 #pragma unroll
@@ -110,7 +104,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
 
   // ---- lane init: prefix energy, inner table, outer cross fields
   E C[kInnerStates];
-  const W EP = lane_init<E, kInnerStates>(v, b, I, p, valid, myc, lane, C);
+  const W EP = lane_init<E, kInnerStates>(v, b, I, local, valid, myc, lane, C);
 
   // ---- outer walk
   // Dp = thr - E_P - X_PO(p, g(t)) is kept instead of the running value itself:
@@ -171,7 +165,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
       W KE;
       if constexpr (std::is_same_v<E, float>) KE = thr - Dp + o.eo;
       else KE = (int64_t)(int32_t)thr - (int64_t)Dp - (int64_t)o.eo;
-      replay<E>(v, b, I, t, p, valid, KE, nthr, lkey, lmask, pub, lane);
+      replay<E>(v, b, I, t, p, valid, KE, nthr, lkey, lmask, pub, myc, lane);
       retune(nthr);
     }
   };
@@ -246,7 +240,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
 template <class E>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_kernel(Views v) {
   using W = typename Ar<E>::W;
-  __shared__ W ctab[kWavesPerBlock][kMaxOuter * kWave];
+  __shared__ W ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   W* myc = ctab[threadIdx.x >> 6];
   const uint64_t total_units = uniform_u64(gp((const Header*)v.hdr)->total_units);
@@ -254,9 +248,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
   uint64_t lmask = ~0ull;
   uint64_t pub = ~0ull;
   int cur = -1;
-  for (;;) {
-    const uint64_t u = next_unit(v, lane);
-    if (u >= total_units) break;
+  WorkIter it(v, total_units);
+  uint64_t u;
+  while (it.next(v, lane, u)) {
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     if (b != cur) {
       if (cur >= 0) flush(v, cur, lkey, lmask, lane);

@@ -83,8 +83,8 @@ def test_tuning_knobs_roundtrip():
     L = _lib.lib()
     old = L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS)
     before = L.qubo_bf_workspace_size(40, 16, 0)
-    assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 16) == 0
-    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == 16
+    assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 14) == 0
+    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == 14
     assert L.qubo_bf_workspace_size(40, 16, 0) > before
     assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 0) == 0
     assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == old
