@@ -211,7 +211,6 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.umap_cap = L.umap_cap;
   v.batch = batch;
   v.nmax = nmax;
-  v.chunk = clampi(batch > 1 ? tuning().chunk_batched : tuning().chunk_single, 1, 1 << 20);
   v.dyn = tuning().dyn != 0;
   return v;
 }
@@ -225,6 +224,7 @@ PlanParams single_params(int kp) {
   pp.kprime = kp;
   pp.waves = kMaxGridWaves;  // replaced by the real grid at launch
   pp.lane_bits = 6;
+  pp.chunk_cap = clampi(t.chunk_single, 1, 1 << 20);
   return pp;
 }
 
@@ -237,6 +237,7 @@ PlanParams batched_params(int kp) {
   pp.kprime = kp;
   pp.waves = kMaxGridWaves;
   pp.lane_bits = 6;
+  pp.chunk_cap = clampi(t.chunk_batched, 1, 1 << 20);
   return pp;
 }
 
@@ -248,6 +249,7 @@ PlanParams grad_params() {
   pp.kprime = 1;
   pp.waves = kMaxGridWaves;
   pp.lane_bits = 6;
+  pp.chunk_cap = clampi(tuning().chunk_batched, 1, 1 << 20);
   return pp;
 }
 
@@ -275,8 +277,8 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
   HIPCHK(launch_prep_inst(v, Q, ldq, stride, is_int, kInner, s));
   HIPCHK(launch_prep_lanes(v, is_int, s));
-  int tw = (int)(steps_hint < 4096 ? steps_hint : 4096);
-  HIPCHK(launch_prep_tables(v, is_int, kInner, tw < 4 ? 4 : tw, s));
+  HIPCHK(launch_seed(v, is_int, s));
+  HIPCHK(launch_prep_tables(v, is_int, kInner, steps_hint, s));
   {
     ProfScope ps("walk_topk", s);
     HIPCHK(launch_walk_topk(v, is_int, waves, s));
@@ -435,7 +437,8 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
   HIPCHK(launch_prep_lanes(v, false, s));
-  HIPCHK(launch_prep_tables(v, false, kInner, (int)(steps_bound < 4096 ? steps_bound : 4096), s));
+  HIPCHK(launch_seed(v, false, s));
+  HIPCHK(launch_prep_tables(v, false, kInner, steps_bound, s));
   {
     ProfScope ps("walk_topk", s);  // minimum pass: E_ref per instance
     HIPCHK(launch_walk_topk(v, false, waves, s));
@@ -470,7 +473,7 @@ int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, pp.inner, s));
   HIPCHK(launch_prep_lanes(v, false, s));
-  HIPCHK(launch_prep_tables(v, false, pp.inner, (int)(steps_bound < 4096 ? steps_bound : 4096), s));
+  HIPCHK(launch_prep_tables(v, false, pp.inner, steps_bound, s));
   {
     ProfScope ps("walk_grad", s);
     HIPCHK(launch_walk_grad(v, beta, logz, waves, np, s));

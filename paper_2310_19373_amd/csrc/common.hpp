@@ -77,7 +77,7 @@ struct Header {
   int32_t batch;
   int32_t nmax;
   int32_t waves;          // waves of the persistent walk grid
-  int32_t pad;
+  int32_t chunk;          // consecutive work units per queue pull
 };
 
 // Per-step uniform data of the outer walk.

@@ -24,7 +24,6 @@ struct Views {
   uint32_t* umap;  // [umap_cap] work unit -> instance, or null (binary search)
   int64_t umap_cap;
   int batch, nmax;
-  int chunk;       // consecutive work units per queue pull
   int dyn;         // 1: atomic work queue, 0: static round-robin of chunks
 };
 
@@ -35,6 +34,7 @@ struct PlanParams {
   int kprime;    // candidate list length
   int waves;     // waves of the persistent walk grid
   int lane_bits; // lane bits wanted (6 normally)
+  int chunk_cap; // largest queue chunk (the planner picks <= this from the unit count)
 };
 
 // plan: bit split, unit/table/slot offsets, counters.  ns == nullptr: one
@@ -49,8 +49,11 @@ hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t 
 // per-instance lane table: contributions of the lane bits to E_P and to the
 // inner / outer cross fields, for each of the 64 lane values.
 hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s);
-// per-step tables of the outer walk.
-hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int grid_waves, hipStream_t s);
+// a-priori threshold per instance from a greedy descent (after prep_inst).
+hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s);
+// per-step tables of the outer walk; steps_bound >= total steps of the plan
+// (sizes the grid only: the kernel reads the exact count from the header).
+hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int64_t steps_bound, hipStream_t s);
 // persistent top-k walk.
 hipError_t launch_walk_topk(const Views& v, bool is_int, int waves, hipStream_t s);
 // merge candidate lists, rescore in float64 / int64, certificate, outputs.

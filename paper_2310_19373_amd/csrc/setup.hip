@@ -14,6 +14,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "wave.hpp"
 
 namespace qbf {
 
@@ -111,6 +112,10 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
     v.hdr->batch = batch;
     v.hdr->nmax = v.nmax;
     v.hdr->waves = pp.waves;
+    // about four pulls per wave or more, so the queue balances the tail
+    int64_t c = su[nt - 1] / ((int64_t)(pp.waves > 0 ? pp.waves : 1) * 4);
+    if (c > pp.chunk_cap) c = pp.chunk_cap;
+    v.hdr->chunk = c < 1 ? 1 : (int32_t)c;
   }
 }
 
@@ -222,6 +227,80 @@ __global__ void __launch_bounds__(64) prep_lanes_kernel(Views v) {
   for (int i = 0; i < kLaneRec; ++i) lt[i] = rec[i];
 }
 
+// Exact value of state x from the (sign-applied) symmetric copy of Q.
+template <class W>
+__device__ W state_energy(const W* qs, int nm, int n, uint64_t x) {
+  W e = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!((x >> i) & 1)) continue;
+    W row = qs[(int64_t)i * nm + i];
+    for (int j = i + 1; j < n; ++j)
+      if ((x >> j) & 1) row += qs[(int64_t)i * nm + j];
+    e += row;
+  }
+  return e;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood 2014), used as a hash.
+__device__ uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// A-priori threshold for instance b.  Each lane runs a greedy one-flip descent
+// from its own start (lane 0 from x = 0); the best local minimum x* and its n
+// one-flip neighbours are n + 1 distinct states, so the K'-th smallest of their
+// values bounds the instance's K'-th smallest value from above.  Published with
+// the float filter's error margin, the bound discards nothing the walk would
+// keep; it only spares each wave the replays of its cold start.
+template <class W>
+__global__ void __launch_bounds__(64) seed_kernel(Views v) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const Inst* I = &v.inst[b];
+  if (I->status != 0) return;
+  const int n = I->n, kp = I->kprime, nm = v.nmax;
+  if (kp > n + 1) return;
+  const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
+  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  uint64_t x = lane == 0 ? 0 : (mix64(((uint64_t)b << 6) | (uint64_t)lane) & all);
+  // descent: every accepted flip lowers the value; at most 4n sweeps
+  for (int sweep = 0; sweep < 4 * n; ++sweep) {
+    bool moved = false;
+    for (int i = 0; i < n; ++i) {
+      W h = qs[(int64_t)i * nm + i];
+      for (int j = 0; j < n; ++j)
+        if (j != i && ((x >> j) & 1)) h += qs[(int64_t)i * nm + j];
+      const W d = ((x >> i) & 1) ? -h : h;
+      if (d < 0) {
+        x ^= 1ull << i;
+        moved = true;
+      }
+    }
+    if (!moved) break;
+  }
+  // best local minimum over the wave, ties to the lower lane
+  double key = (double)state_energy(qs, nm, n, x);
+  uint64_t mask = x;
+  wave_sort(key, mask, lane);
+  const uint64_t xs = readlane_u64(mask, 0);
+  // lane i < n: neighbour x* ^ e_i; lane n: x* itself
+  key = __builtin_inf();
+  mask = ~0ull;
+  if (lane <= n) {
+    mask = lane < n ? (xs ^ (1ull << lane)) : xs;
+    key = (double)state_energy(qs, nm, n, mask);
+  }
+  wave_sort(key, mask, lane);
+  const double vk = readlane_f64(key, kp - 1);
+  if (lane == 0 && vk < __builtin_inf()) {
+    // float: the walk's filter error (eps) plus float64 rounding of the sums here
+    const double margin = std::is_same_v<W, double> ? I->eps + 1e-12 * I->sumabs : 0.0;
+    v.gthr[b] = enc_key(vk + margin);
+  }
+}
+
 __device__ int find_by_tab(const Views& v, int64_t s) {
   int lo = 0, hi = v.batch;
   while (hi - lo > 1) {
@@ -234,46 +313,60 @@ __device__ int find_by_tab(const Views& v, int64_t s) {
 
 template <class W, class E>
 __global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
-  const int lane = threadIdx.x & 63;
+  // A wave takes 64 consecutive steps: lane i computes the scalars of step
+  // s0 + i (its own instance, its own O(no^2) sum), parks H in LDS, and the
+  // wave then writes the 64 table rows one coalesced row at a time.
+  __shared__ W hs[4][6][kWave];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t total = v.hdr->total_steps;
   const int width = 1 << inner, per = width / 16;
-  for (int64_t s = wave; s < total; s += nwaves) {
-    const int b = v.batch == 1 ? 0 : find_by_tab(v, s);
-    const Inst* I = &v.inst[b];
-    const int64_t t = s - I->tab_off;
+  E* tab = (E*)v.tab;
+  for (int64_t s0 = wave * kWave; s0 < total; s0 += nwaves * kWave) {
+    const int64_t s = s0 + lane;
     W H[6] = {0, 0, 0, 0, 0, 0};
     W eo = 0;
-    const int B = I->B, no = I->no;
-    if (I->status == 0 && t < (int64_t(1) << no)) {
-      const W* qs = (const W*)v.qs + (int64_t)b * v.nmax * v.nmax;
-      const uint64_t o = gray((uint64_t)t);
-      for (int l = 0; l < no; ++l) {
-        if (!((o >> l) & 1)) continue;
-        const int a = B + l;
-        W row = qs[(int64_t)a * v.nmax + a];
-        for (int l2 = l + 1; l2 < no; ++l2)
-          if ((o >> l2) & 1) row += qs[(int64_t)a * v.nmax + B + l2];
-        eo += row;
+    if (s < total) {
+      const int b = v.batch == 1 ? 0 : find_by_tab(v, s);
+      const Inst* I = &v.inst[b];
+      const int64_t t = s - I->tab_off;
+      const int B = I->B, no = I->no;
+      if (I->status == 0 && t < (int64_t(1) << no)) {
+        const W* qs = (const W*)v.qs + (int64_t)b * v.nmax * v.nmax;
+        const uint64_t o = gray((uint64_t)t);
+        for (int l = 0; l < no; ++l) {
+          if (!((o >> l) & 1)) continue;
+          const int a = B + l;
+          W row = qs[(int64_t)a * v.nmax + a];
+          for (int l2 = l + 1; l2 < no; ++l2)
+            if ((o >> l2) & 1) row += qs[(int64_t)a * v.nmax + B + l2];
+          eo += row;
 #pragma unroll
-        for (int u = 0; u < 6; ++u)
-          if (u < B) H[u] += qs[(int64_t)u * v.nmax + a];
+          for (int u = 0; u < 6; ++u)
+            if (u < B) H[u] += qs[(int64_t)u * v.nmax + a];
+        }
       }
-    }
-    W tj = 0;
+      StepRec* r = &v.rec[s];
+      r->eo = (double)eo;
 #pragma unroll
-    for (int u = 0; u < 6; ++u)
-      if (u < B && ((lane >> u) & 1)) tj += H[u];
-    if (lane < width) ((E*)v.tab)[s * width + (lane & 15) * per + (lane >> 4)] = (E)tj;
-    if (lane == 0) {
-      StepRec r;
-      r.eo = (double)eo;
-      for (int u = 0; u < 6; ++u) r.h[u] = (double)H[u];
-      r.neo = (int32_t)(-eo);
-      r.pad = 0;
-      v.rec[s] = r;
+      for (int u = 0; u < 6; ++u) r->h[u] = (double)H[u];
+      r->neo = (int32_t)(-eo);
+      r->pad = 0;
     }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) hs[w][u][lane] = H[u];
+    __builtin_amdgcn_wave_barrier();
+    const int nst = (int)min<int64_t>(kWave, total - s0);
+    for (int k = 0; k < nst; ++k) {
+      // H_u is zero for u >= B, so summing every set lane bit is the same sum
+      W tj = 0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        if ((lane >> u) & 1) tj += hs[w][u][k];
+      if (lane < width) tab[(s0 + k) * width + (lane & 15) * per + (lane >> 4)] = (E)tj;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -309,8 +402,19 @@ hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int grid_waves, hipStream_t s) {
-  const int blocks = max(1, grid_waves / 4);
+hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s) {
+  if (is_int)
+    hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), 0, s, v);
+  else
+    hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(64), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int64_t steps_bound, hipStream_t s) {
+  // one wave per 64 steps, at most 8 waves per compute unit
+  int64_t waves = (steps_bound + kWave - 1) / kWave;
+  if (waves > 2048) waves = 2048;
+  const int blocks = waves > 4 ? (int)((waves + 3) / 4) : 1;
   if (is_int)
     hipLaunchKernelGGL((prep_tables_kernel<int64_t, int32_t>), dim3(blocks), dim3(256), 0, s, v, inner);
   else

@@ -63,7 +63,7 @@ __device__ __forceinline__ uint64_t next_unit(const Views& v, int lane) {
   return uniform_u64(r);
 }
 
-// Work distribution of the persistent walks: chunks of v.chunk consecutive
+// Work distribution of the persistent walks: chunks of consecutive
 // units, taken from the atomic queue (v.dyn) or statically (wave w of G takes
 // chunks w, w+G, ...).  Consecutive units of a chunk mostly belong to one
 // instance, so a wave's candidate list carries over between them.
@@ -73,7 +73,7 @@ struct WorkIter {
   bool dyn;
   __device__ WorkIter(const Views& v, uint64_t total_units) {
     total = total_units;
-    chunk = (uint64_t)(v.chunk > 0 ? v.chunk : 1);
+    chunk = (uint64_t)(uint32_t)uniform_i32(gp((const Header*)v.hdr)->chunk);
     dyn = v.dyn != 0;
     next_static = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     stride = (int64_t)gridDim.x * kWavesPerBlock;
