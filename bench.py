@@ -16,6 +16,7 @@ same workload.  Secondary workloads (batched, log-partition) are reported under
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +33,41 @@ sys.path.insert(0, ROOT)
 ALG_OPS_PER_STATE = 1.5
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 non-packed VALU lane-ops/s.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+# HBM bytes per walk launch come from the committed rocprofv3 counter summary
+# (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings); they are
+# reported only while the walk's sources still hash to the profiled ones.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "walk_topk_n40_f32_k16_counters.md")
+WALK_SOURCES = ("paper_2310_19373_amd/csrc/walk_topk.hip", "paper_2310_19373_amd/csrc/walk.hpp",
+                "paper_2310_19373_amd/csrc/wave.hpp", "paper_2310_19373_amd/csrc/common.hpp",
+                "paper_2310_19373_amd/csrc/launch.hpp", "paper_2310_19373_amd/build.py")
+
+
+def walk_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for rel in WALK_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """Bytes per walk launch from the counter summary, or None when it is
+    missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            key, sep, val = line.strip().strip("-* `").partition(":")
+            if sep:
+                fields[key.strip("` ")] = val.strip(" `")
+    if fields.get("kernel_sources_sha256") != walk_sources_sha256():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(Q, n, k):
@@ -62,26 +98,38 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def extra_batched(dev):
+def extra_batched(dev, plain_loop=True):
     """Config 4: 4096 QUBOs, n uniform in [12, 28], k=1 -- one captured graph
     replay vs one qubo_bf_solve call per instance on the same stream."""
     import torch
 
     from paper_2310_19373_amd import _lib, api, inputs
 
+    from paper_2310_19373_amd import autotune
+
     Q, ns = inputs.batched_4096()
     states = float(sum(1 << int(n) for n in ns))
-    solver = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=True)
-    solver.load(Q, ns)
-    solver.run()
-    torch.cuda.synchronize()
-    solver.results()
-    _lib.prof_enable(True)
-    _lib.prof_collect("walk_topk")
-    t_batched = _time(solver.run, 5)
-    _lib.prof_enable(False)
-    wms, wn = _lib.prof_collect("walk_topk")
-    e_b = solver.energies.clone()
+    names = list(autotune.BATCHED_SPACE)
+    with autotune.keep_tuning(names):
+        # the launch shape is picked by the autotuner on this batch
+        tune = autotune.tune_batched(Q, ns, k=1, reps=3)
+        solver = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=True)
+        solver.load(Q, ns)
+        solver.run()
+        torch.cuda.synchronize()
+        solver.results()
+        t_batched = _time(solver.run, 5)
+        e_b = solver.energies.clone()
+        # kernel time of the walk, from an uncaptured run of the same sequence
+        eager = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=False)
+        eager.load(Q, ns)
+        eager.run()
+        torch.cuda.synchronize()
+        _lib.prof_enable(True)
+        _lib.prof_collect("walk_topk")
+        _time(eager.run, 3)
+        _lib.prof_enable(False)
+        wms, wn = _lib.prof_collect("walk_topk")
     # plain: one full solve (its own launch sequence) per instance
     L = _lib.lib()
     Qs = [torch.from_numpy(np.ascontiguousarray(Q[b, :int(n), :int(n)])).to(dev) for b, n in enumerate(ns)]
@@ -97,16 +145,19 @@ def extra_batched(dev):
             _lib.check(L.qubo_bf_solve(Qs[b].data_ptr(), int(n), int(n), _lib.QUBO_F32, 1, en[b].data_ptr(),
                                        mk[b].data_ptr(), st[b:b + 1].data_ptr(), ws.data_ptr(), ws_bytes, stream))
 
-    plain()
-    t_plain = _time(plain, 2)
-    same = bool(torch.equal(en, e_b))
+    t_plain, same = float("nan"), None
+    if plain_loop:
+        plain()
+        t_plain = _time(plain, 2)
+        same = bool(torch.equal(en, e_b))
     return {"workload": "4096 QUBOs, n uniform in [12,28] (seed 3), float32 N(0,1), k=1",
             "states": states, "batched_ms": t_batched * 1e3, "batched_states_per_s": states / t_batched,
             "walk_ms": wms / max(wn, 1), "plain_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched,
-            "identical_to_plain": same}
+            "identical_to_plain": same, "tuned": tune.best, "untuned_ms": tune.start_ms,
+            "tune_trials": len(tune.trials)}
 
 
-def extra_logz(dev):
+def extra_logz(dev, plain_loop=True):
     """Config 5: 256 QUBOs n=24 x beta in {0.5,1,4}: one batched logZ forward +
     backward vs one forward + backward call per (instance, beta) pair."""
     import torch
@@ -138,8 +189,10 @@ def extra_logz(dev):
         for p in range(len(beta)):
             fwd_bwd(Qt[p:p + 1], bt[p:p + 1], one)
 
-    plain()
-    t_plain = _time(plain, 1)
+    t_plain = float("nan")
+    if plain_loop:
+        plain()
+        t_plain = _time(plain, 1)
     states = float(len(beta)) * (1 << 24)
     return {"workload": "768 (instance, beta) pairs: 256 QUBOs n=24 float32 N(0,1/n) (seed 4) x beta {0.5,1,4}",
             "states_per_pass": states, "batched_fwd_bwd_ms": t_batched * 1e3,
@@ -153,10 +206,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the batched and log-partition workloads against one call per instance")
+    ap.add_argument("--only", choices=("batched", "logz"),
+                    help="run only that secondary workload, without the one-call-per-instance loop")
+    ap.add_argument("--sources-sha", action="store_true", help="print the walk sources' sha256 and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration for HBM bytes)")
     args = ap.parse_args()
+    if args.sources_sha:
+        print(walk_sources_sha256())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the enumeration shards by prefix "
               "bits across GPUs, which this build does not run", file=sys.stderr)
@@ -176,6 +236,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
+    if args.only:
+        leg = extra_batched if args.only == "batched" else extra_logz
+        print(json.dumps({args.only: leg(dev, plain_loop=False)}), flush=True)
         return
     Q, xstar = inputs.single_n40_f32_planted()
     n, k = 40, 16
@@ -231,7 +295,7 @@ def main():
         "config": {"workload": "single QUBO n=40, float32 N(0,1/n) + planted minimiser (seed 2), k=16, "
                                "2^40 states per step, float64 rescoring of the top candidates"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU lane-op/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": committed_traffic(),
                      "kernel": "walk_topk", "kernel_ms": walk_avg_s * 1e3,
                      "ops_per_state": ALG_OPS_PER_STATE},
     }

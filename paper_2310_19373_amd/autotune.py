@@ -1,0 +1,269 @@
+"""Autotuner for the launch shape of the enumeration kernels.
+
+The walk splits each instance's n bits into inner bits (6, the per-lane
+table), lane bits (6), outer bits (Gray-walked inside a work unit) and unit
+bits (the prefix that numbers the work units, Sec. 3.1's split of the search
+space into independent sub-walks).  How many bits go to the outer walk versus
+the unit prefix, how many waves per compute unit the persistent grid runs and
+how many units a wave takes per queue pull all change speed, never results.
+The best choice depends on the mix of instance sizes, so it is measured on the
+caller's own batch:
+
+    res = autotune.tune_batched(Qpad, ns, k=1)     # applies the best setting
+    res.best  -> {"batched_outer": 8, "waves_per_cu": 12, "chunk_batched": 8}
+
+The search is a coordinate descent from the current setting over a small grid
+per knob.  Every candidate's outputs (energies, masks, status) must equal those
+of the starting setting bit for bit, else the candidate is rejected.  Results
+can be kept in a JSON file keyed by a workload signature and re-applied with
+``apply_cached``.
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+
+# knob name -> C ABI identifier (qubo_bf_set_tuning)
+KNOBS = {
+    "single_outer": _lib.TUNE_SINGLE_OUTER_BITS,
+    "single_unit": _lib.TUNE_SINGLE_UNIT_BITS,
+    "batched_outer": _lib.TUNE_BATCHED_OUTER_BITS,
+    "waves_per_cu": _lib.TUNE_WAVES_PER_CU,
+    "chunk_single": _lib.TUNE_CHUNK_SINGLE,
+    "chunk_batched": _lib.TUNE_CHUNK_BATCHED,
+}
+
+BATCHED_SPACE = {
+    "batched_outer": (6, 7, 8, 9, 10),
+    "waves_per_cu": (4, 8, 12),
+    "chunk_batched": (2, 4, 8, 16),
+}
+
+SINGLE_SPACE = {
+    "single_outer": (10, 11, 12, 13, 14),
+    "waves_per_cu": (8, 12),
+    "chunk_single": (1, 2, 4, 8),
+}
+
+
+@dataclass
+class TuneResult:
+    best: dict
+    ms: float
+    start: dict
+    start_ms: float
+    signature: dict
+    trials: list = field(default_factory=list)  # (setting, ms or None, note)
+
+
+def current(names) -> dict:
+    return {nm: _lib.get_tuning(KNOBS[nm]) for nm in names}
+
+
+def apply(setting: dict):
+    for nm, val in setting.items():
+        _lib.set_tuning(KNOBS[nm], int(val))
+
+
+class keep_tuning:
+    """Context manager restoring the listed knobs on exit."""
+
+    def __init__(self, names):
+        self.names = list(names)
+
+    def __enter__(self):
+        self.saved = current(self.names)
+        return self
+
+    def __exit__(self, *exc):
+        apply(self.saved)
+        return False
+
+
+def coordinate_descent(space: dict, start: dict, evaluate, rounds: int = 2):
+    """Minimise evaluate(setting) -> float | None (None = rejected) one knob at
+    a time over the candidate values in ``space``, starting from ``start``.
+    Returns (best setting, best cost, trials).  Every setting is evaluated at
+    most once."""
+    seen = {}
+    trials = []
+
+    def cost(setting):
+        key = tuple(sorted(setting.items()))
+        if key not in seen:
+            c = evaluate(dict(setting))
+            seen[key] = c
+            trials.append((dict(setting), c))
+        return seen[key]
+
+    best = dict(start)
+    best_c = cost(best)
+    if best_c is None:
+        raise RuntimeError("the starting setting was rejected")
+    for _ in range(rounds):
+        moved = False
+        for nm, values in space.items():
+            for val in values:
+                if val == best[nm]:
+                    continue
+                cand = dict(best)
+                cand[nm] = val
+                c = cost(cand)
+                if c is not None and c < best_c:
+                    best, best_c, moved = cand, c, True
+        if not moved:
+            break
+    return best, best_c, trials
+
+
+def batched_signature(ns, k: int, dtype: str, device_name: str = "") -> dict:
+    ns = np.asarray(ns, dtype=np.int64)
+    hist = np.bincount(ns, minlength=int(ns.max()) + 1 if ns.size else 1)
+    return {"kind": "batched", "batch": int(ns.size), "nmax": int(ns.max()) if ns.size else 0, "k": int(k),
+            "dtype": dtype, "states": float(np.sum(np.ldexp(1.0, ns))),
+            "n_hist": {str(i): int(c) for i, c in enumerate(hist) if c}, "device": device_name}
+
+
+def _sig_key(sig: dict) -> str:
+    return json.dumps(sig, sort_keys=True)
+
+
+def save_cached(path: str, sig: dict, best: dict, ms: float):
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data[_sig_key(sig)] = {"best": best, "ms": ms}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load_cached(path: str, sig: dict):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(_sig_key(sig))
+    return None if ent is None else ent["best"]
+
+
+def apply_cached(path: str, sig: dict) -> bool:
+    best = load_cached(path, sig)
+    if best is None:
+        return False
+    apply(best)
+    return True
+
+
+def _median_ms(torch, fn, reps: int, warmup: int) -> float:
+    for _ in range(warmup):
+        fn()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def tune_batched(Qpad, ns, k: int = 1, *, space: dict | None = None, reps: int = 3, warmup: int = 1,
+                 apply_best: bool = True, cache: str | None = None, rounds: int = 2) -> TuneResult:
+    """Times qubo_bf_solve_batched (one captured graph per setting) on this
+    batch and keeps the fastest setting whose outputs equal the starting
+    setting's."""
+    import torch
+
+    from .api import BatchedSolver, _as_device
+
+    space = BATCHED_SPACE if space is None else space
+    Qd = _as_device(Qpad)
+    nsd = _as_device(ns, torch.int32, Qd.device)
+    batch, nmax = Qd.shape[0], Qd.shape[1]
+    dtype = "f32" if Qd.dtype == torch.float32 else "i32"
+    sig = batched_signature(nsd.cpu().numpy(), k, dtype, torch.cuda.get_device_name(Qd.device))
+    names = list(space)
+    ref = {}
+
+    def evaluate(setting):
+        apply(setting)
+        solver = BatchedSolver(batch, nmax, k, Qd.dtype, Qd.device, graph=True)
+        solver.Q = Qd
+        solver.ns = nsd
+        solver.run()
+        torch.cuda.synchronize(Qd.device)
+        out = (solver.energies.clone(), solver.masks.clone(), solver.status.clone())
+        if not ref:
+            ref["out"] = out
+        elif not all(torch.equal(x, y) for x, y in zip(out, ref["out"])):
+            return None
+        return _median_ms(torch, solver.run, reps, warmup)
+
+    with keep_tuning(names):
+        start = current(names)
+        best, best_ms, trials = coordinate_descent(space, start, evaluate, rounds)
+    start_ms = trials[0][1]
+    if apply_best:
+        apply(best)
+    if cache:
+        save_cached(cache, sig, best, best_ms)
+    return TuneResult(best=best, ms=best_ms, start=start, start_ms=start_ms, signature=sig,
+                      trials=[(s, c, "rejected" if c is None else "") for s, c in trials])
+
+
+def tune_single(Q, k: int = 1, *, space: dict | None = None, reps: int = 3, warmup: int = 1,
+                apply_best: bool = True, rounds: int = 1) -> TuneResult:
+    """The same search for qubo_bf_solve on one instance."""
+    import torch
+
+    from .api import _as_device, _stream
+
+    space = SINGLE_SPACE if space is None else space
+    Qd = _as_device(Q)
+    n = Qd.shape[0]
+    dt = _lib.QUBO_F32 if Qd.dtype == torch.float32 else _lib.QUBO_I32
+    L = _lib.lib()
+    d = Qd.device
+    en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=d)
+    mk = torch.empty(k, dtype=torch.int64, device=d)
+    st = torch.empty(1, dtype=torch.int32, device=d)
+    names = list(space)
+    ref = {}
+
+    def evaluate(setting):
+        apply(setting)
+        wsb = L.qubo_bf_workspace_size(n, k, dt)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=d)
+
+        def run():
+            _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, Qd.stride(0), dt, k, en.data_ptr(), mk.data_ptr(),
+                                       st.data_ptr(), ws.data_ptr(), wsb, _stream(d)))
+
+        run()
+        torch.cuda.synchronize(d)
+        out = (en.clone(), mk.clone(), st.clone())
+        if not ref:
+            ref["out"] = out
+        elif not all(torch.equal(x, y) for x, y in zip(out, ref["out"])):
+            return None
+        return _median_ms(torch, run, reps, warmup)
+
+    with keep_tuning(names):
+        start = current(names)
+        best, best_ms, trials = coordinate_descent(space, start, evaluate, rounds)
+    if apply_best:
+        apply(best)
+    sig = {"kind": "single", "n": int(n), "k": int(k), "dtype": "f32" if dt == _lib.QUBO_F32 else "i32",
+           "device": torch.cuda.get_device_name(d)}
+    return TuneResult(best=best, ms=best_ms, start=start, start_ms=trials[0][1], signature=sig,
+                      trials=[(s, c, "rejected" if c is None else "") for s, c in trials])

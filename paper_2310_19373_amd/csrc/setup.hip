@@ -257,21 +257,26 @@ __device__ uint64_t mix64(uint64_t z) {
 // keep; it only spares each wave the replays of its cold start.
 template <class W>
 __global__ void __launch_bounds__(64) seed_kernel(Views v) {
+  extern __shared__ unsigned char seed_lds[];
   const int b = blockIdx.x, lane = threadIdx.x;
   const Inst* I = &v.inst[b];
   if (I->status != 0) return;
   const int n = I->n, kp = I->kprime, nm = v.nmax;
   if (kp > n + 1) return;
-  const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
+  // the instance's n x n block, staged in LDS (row stride n)
+  W* qs = (W*)seed_lds;
+  const W* qg = (const W*)v.qs + (int64_t)b * nm * nm;
+  for (int e = lane; e < n * n; e += kWave) qs[e] = qg[(int64_t)(e / n) * nm + e % n];
+  __syncthreads();
   const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
   uint64_t x = lane == 0 ? 0 : (mix64(((uint64_t)b << 6) | (uint64_t)lane) & all);
   // descent: every accepted flip lowers the value; at most 4n sweeps
   for (int sweep = 0; sweep < 4 * n; ++sweep) {
     bool moved = false;
     for (int i = 0; i < n; ++i) {
-      W h = qs[(int64_t)i * nm + i];
+      W h = qs[i * n + i];
       for (int j = 0; j < n; ++j)
-        if (j != i && ((x >> j) & 1)) h += qs[(int64_t)i * nm + j];
+        if (j != i && ((x >> j) & 1)) h += qs[i * n + j];
       const W d = ((x >> i) & 1) ? -h : h;
       if (d < 0) {
         x ^= 1ull << i;
@@ -281,7 +286,7 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
     if (!moved) break;
   }
   // best local minimum over the wave, ties to the lower lane
-  double key = (double)state_energy(qs, nm, n, x);
+  double key = (double)state_energy(qs, n, n, x);
   uint64_t mask = x;
   wave_sort(key, mask, lane);
   const uint64_t xs = readlane_u64(mask, 0);
@@ -290,7 +295,7 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   mask = ~0ull;
   if (lane <= n) {
     mask = lane < n ? (xs ^ (1ull << lane)) : xs;
-    key = (double)state_energy(qs, nm, n, mask);
+    key = (double)state_energy(qs, n, n, mask);
   }
   wave_sort(key, mask, lane);
   const double vk = readlane_f64(key, kp - 1);
@@ -403,10 +408,11 @@ hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s) {
 }
 
 hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)v.nmax * (size_t)v.nmax;  // both paths hold 8-byte entries
   if (is_int)
-    hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), 0, s, v);
+    hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), lds, s, v);
   else
-    hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(64), 0, s, v);
+    hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(64), lds, s, v);
   return hipGetLastError();
 }
 
