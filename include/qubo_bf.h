@@ -151,6 +151,9 @@ const char* qubo_version(void);
  *   QUBO_TUNE_CHUNK_SINGLE        work units per queue pull, single solve
  *   QUBO_TUNE_CHUNK_BATCHED       work units per queue pull, batched / logZ
  *   QUBO_TUNE_DYNAMIC_QUEUE       1: atomic work queue; -1: static assignment
+ *   QUBO_TUNE_LOGZ_FACTORED       1: log-partition walks may use the factored
+ *                                 form (one FMA per state); -1: always one exp
+ *                                 per state (same results within rounding)
  * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)
  * set the initial values.  Returns QUBO_OK or QUBO_ERR_INVALID_ARG.
  */
@@ -162,7 +165,8 @@ enum {
   QUBO_TUNE_KPRIME = 5,
   QUBO_TUNE_CHUNK_SINGLE = 6,
   QUBO_TUNE_CHUNK_BATCHED = 7,
-  QUBO_TUNE_DYNAMIC_QUEUE = 8
+  QUBO_TUNE_DYNAMIC_QUEUE = 8,
+  QUBO_TUNE_LOGZ_FACTORED = 9
 };
 int qubo_bf_set_tuning(int knob, int value);
 int qubo_bf_get_tuning(int knob);

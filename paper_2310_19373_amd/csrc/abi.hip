@@ -48,6 +48,7 @@ struct Tuning {
   int chunk_single = 4;
   int chunk_batched = 8;
   int dyn = 1;
+  int logz_factored = 1;
 };
 
 int env_int(const char* name, int dflt) {
@@ -67,6 +68,7 @@ Tuning& tuning() {
     d.chunk_single = env_int("QUBO_BF_CHUNK_SINGLE", d.chunk_single);
     d.chunk_batched = env_int("QUBO_BF_CHUNK_BATCHED", d.chunk_batched);
     d.dyn = env_int("QUBO_BF_DYNAMIC_QUEUE", d.dyn);
+    d.logz_factored = env_int("QUBO_BF_LOGZ_FACTORED", d.logz_factored);
     return d;
   }();
   return t;
@@ -149,14 +151,15 @@ SplitH split_host(int n, const PlanParams& pp) {
 }
 
 struct Layout {
-  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, slots, part, lt, umap, total;
+  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, slots, part, lt, umap, etab, tref, total;
   int64_t umap_cap;
 };
 
 constexpr int64_t kUnitMapMax = int64_t(1) << 24;  // unit -> instance map entries
 
 // Worst case over n <= nmax (steps and units grow with n).
-Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_unit, int64_t part_per_inst) {
+Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_unit, int64_t part_per_inst,
+                   bool exp_tables = false) {
   const SplitH s = split_host(nmax, pp);
   const int64_t steps = int64_t(1) << s.no;
   const int64_t units = int64_t(1) << s.tb;
@@ -189,6 +192,13 @@ Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_u
   L.umap = o;
   L.umap_cap = (batch > 1 && (int64_t)batch * units <= kUnitMapMax) ? (int64_t)batch * units : 0;
   o += al(4 * (size_t)L.umap_cap);
+  L.etab = L.tref = 0;
+  if (exp_tables) {
+    L.etab = o;
+    o += al(4 * (size_t)batch * steps * width);
+    L.tref = o;
+    o += al(8 * (size_t)batch * steps);
+  }
   L.total = o;
   return L;
 }
@@ -209,6 +219,9 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.lt = p + L.lt;
   v.umap = L.umap_cap > 0 ? (uint32_t*)(p + L.umap) : nullptr;
   v.umap_cap = L.umap_cap;
+  v.etab = L.etab ? (void*)(p + L.etab) : nullptr;
+  v.tref = L.tref ? (double*)(p + L.tref) : nullptr;
+  v.factor = L.etab && tuning().logz_factored > 0;
   v.batch = batch;
   v.nmax = nmax;
   v.dyn = tuning().dyn != 0;
@@ -307,6 +320,7 @@ int qubo_bf_set_tuning(int knob, int value) {
     case QUBO_TUNE_CHUNK_SINGLE: t.chunk_single = value > 0 ? value : d.chunk_single; break;
     case QUBO_TUNE_CHUNK_BATCHED: t.chunk_batched = value > 0 ? value : d.chunk_batched; break;
     case QUBO_TUNE_DYNAMIC_QUEUE: t.dyn = value > 0 ? 1 : (value < 0 ? 0 : d.dyn); break;
+    case QUBO_TUNE_LOGZ_FACTORED: t.logz_factored = value > 0 ? 1 : (value < 0 ? 0 : d.logz_factored); break;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
   return QUBO_OK;
@@ -323,6 +337,7 @@ int qubo_bf_get_tuning(int knob) {
     case QUBO_TUNE_CHUNK_SINGLE: return t.chunk_single;
     case QUBO_TUNE_CHUNK_BATCHED: return t.chunk_batched;
     case QUBO_TUNE_DYNAMIC_QUEUE: return t.dyn;
+    case QUBO_TUNE_LOGZ_FACTORED: return t.logz_factored;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
 }
@@ -414,8 +429,8 @@ int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns,
 
 size_t qubo_logz_workspace_size(int batch, int nmax) {
   if (batch < 1 || nmax < 1 || nmax > 32) return 0;
-  const size_t f = make_layout(batch, nmax, batched_params(1), 1, 0).total;
-  const size_t g = make_layout(batch, nmax, grad_params(), logz_npairs(nmax), 0).total;
+  const size_t f = make_layout(batch, nmax, batched_params(1), 1, 0, true).total;
+  const size_t g = make_layout(batch, nmax, grad_params(), logz_npairs(nmax), 0, true).total;
   return f > g ? f : g;
 }
 
@@ -427,7 +442,7 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   const size_t need = qubo_logz_workspace_size(batch, nmax);
   if (ws_bytes < need) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
   PlanParams pp = batched_params(1);
-  const Layout L = make_layout(batch, nmax, pp, 1, 0);
+  const Layout L = make_layout(batch, nmax, pp, 1, 0, true);
   const Views v = make_views(ws, L, batch, nmax);
   hipStream_t s = (hipStream_t)hip_stream;
   const int waves = grid_waves();
@@ -437,18 +452,13 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
   HIPCHK(launch_prep_lanes(v, false, s));
-  HIPCHK(launch_seed(v, false, s));
   HIPCHK(launch_prep_tables(v, false, kInner, steps_bound, s));
-  {
-    ProfScope ps("walk_topk", s);  // minimum pass: E_ref per instance
-    HIPCHK(launch_walk_topk(v, false, waves, s));
-  }
-  HIPCHK(launch_reset_queue(v, s));
+  HIPCHK(launch_prep_exp_tables(v, beta, kInner, steps_bound, s));
   {
     ProfScope ps("walk_exp", s);
-    HIPCHK(launch_walk_exp(v, beta, nullptr, waves, s));
+    HIPCHK(launch_walk_exp(v, beta, waves, s));
   }
-  HIPCHK(launch_finalize_logz(v, beta, nullptr, logz, status, s));
+  HIPCHK(launch_finalize_logz(v, beta, logz, status, s));
   return QUBO_OK;
 }
 
@@ -463,7 +473,7 @@ int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   if (ws_bytes < need) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
   PlanParams pp = grad_params();
   const int np = logz_npairs(nmax);
-  const Layout L = make_layout(batch, nmax, pp, np, 0);
+  const Layout L = make_layout(batch, nmax, pp, np, 0, true);
   const Views v = make_views(ws, L, batch, nmax);
   hipStream_t s = (hipStream_t)hip_stream;
   const int waves = grid_waves();
@@ -474,6 +484,7 @@ int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, pp.inner, s));
   HIPCHK(launch_prep_lanes(v, false, s));
   HIPCHK(launch_prep_tables(v, false, pp.inner, steps_bound, s));
+  HIPCHK(launch_prep_exp_tables(v, beta, pp.inner, steps_bound, s));
   {
     ProfScope ps("walk_grad", s);
     HIPCHK(launch_walk_grad(v, beta, logz, waves, np, s));

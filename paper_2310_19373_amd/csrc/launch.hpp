@@ -22,6 +22,9 @@ struct Views {
   double* part;    // per-unit partial sums (logZ forward) / per-wave moments (gradient)
   void* lt;        // [batch][64][kLaneRec] lane table (double or int64), see prep_lanes
   uint32_t* umap;  // [umap_cap] work unit -> instance, or null (binary search)
+  void* etab;      // log-partition: factor table b(t, j), layout of tab (float), or null
+  double* tref;    // log-partition: min_j T'(g(t); j) + E_O(g(t)) per step, or null
+  int factor;      // log-partition: 1 = factored form allowed
   int64_t umap_cap;
   int batch, nmax;
   int dyn;         // 1: atomic work queue, 0: static round-robin of chunks
@@ -61,11 +64,11 @@ hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int6
                                 int k, void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,
                                 hipStream_t s);
 
-// log-partition forward: min pass (walk_topk, k = 1) then exp pass.
-hipError_t launch_finalize_min(const Views& v, double* eref, hipStream_t s);
-hipError_t launch_walk_exp(const Views& v, const float* beta, const double* eref, int waves, hipStream_t s);
-hipError_t launch_finalize_logz(const Views& v, const float* beta, const double* eref, double* logz,
-                                int32_t* status, hipStream_t s);
+// log-partition: factor tables (after prep_tables), forward walk, finalize.
+hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,
+                                 hipStream_t s);
+hipError_t launch_walk_exp(const Views& v, const float* beta, int waves, hipStream_t s);
+hipError_t launch_finalize_logz(const Views& v, const float* beta, double* logz, int32_t* status, hipStream_t s);
 // log-partition backward: moment walk (inner = 5) then assembly.
 hipError_t launch_walk_grad(const Views& v, const float* beta, const double* logz, int64_t total_waves,
                             int n_moments, hipStream_t s);

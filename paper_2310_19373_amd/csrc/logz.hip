@@ -8,12 +8,21 @@
 // T'(g(t); j) and the per-lane scalar KE.  The instance is walked on sign(beta)*Q
 // with |beta|, so the exponents stay bounded for any sign of beta.
 //
-// Forward: a k = 1 top-k walk first publishes E_ref = min_x f(x) (the
-// instance threshold); then every state contributes 2^a with
-// a = -|beta| log2(e) (e_j + KE - E_ref) <= ~0, summed per lane in float32
-// over the 64 inner states and in float64 over the steps, reduced over the
-// wave and written per work unit; the finalize sums the units in order and
-// returns logZ = -|beta| E_ref + ln S.
+// Forward: a streaming log-sum-exp, no separate minimum pass.  Each lane keeps
+// a reference energy r and the sum s = sum 2^(-bb (f - r)) of its states
+// (bb = |beta| log2 e), rebasing r when a block lies far below it.  A work
+// unit reduces its lanes to log2 of its sum; the finalize merges the units by
+// log-sum-exp in float64.  Two forms of the per-state work:
+//   * factored (units whose per-lane inner range bb (max C' - min C') is at
+//     most kSafeExp2): the weight of state (t, j) splits as
+//       a_j * b(t, j) * 2^(c_t),  a_j = 2^(-bb (C'(j) - min C')),
+//       b(t, j) = 2^(-bb (T'(g(t); j) - min_j T'(g(t); .))),
+//     so a block of 64 states is one 64-term dot product (one DPP-broadcast
+//     FMA per state) and one exp per step.  The range bound keeps the block's
+//     largest product above 2^-kSafeExp2, so float32 underflow only drops
+//     terms below 2^-126 of an already represented block sum;
+//   * direct (other units): e_j = C'(j) + T'(g(t); j), the block minimum
+//     rebases r, and every state takes one exp2.
 //
 // Backward: each state's weight w = p(x) = 2^(-|beta| log2(e) (e_j + KE) -
 // logZ log2(e)).  Per lane and unit the walk accumulates
@@ -50,12 +59,87 @@ __device__ __forceinline__ float wave_sum(float x) {
 
 // ------------------------------------------------------------ exp-sum walk
 
+// bb (max C' - min C') bound of the factored form (see the file comment).
+constexpr float kSafeExp2 = 84.f;
+// A block whose lower bound lies more than 2^kRebase below the lane's
+// reference energy moves the reference there.
+constexpr double kRebase = 32.0;
+
 // acc[Q&3] += 2^(fma(C'(16K+Q) + T'(16K+Q), nb, cst)) for Q = 0..15.
 template <int K, int Q>
 __device__ __forceinline__ void block_exp(float (&acc)[4], float t, const float* C, float nb, float cst) {
   const float e = row_bcast<Q>(t) + C[16 * K + Q];
   acc[Q & 3] += exp2_fast(__builtin_fmaf(e, nb, cst));
   if constexpr (Q + 1 < 16) block_exp<K, Q + 1>(acc, t, C, nb, cst);
+}
+
+// acc[Q&3] += a(16K+Q) * b(16K+Q) for Q = 0..15, b broadcast from lane Q of
+// each 16-lane row: one v_fmac_f32 with a DPP row broadcast per state (the
+// compiler does not fold the broadcast into an FMA by itself).  The DPP
+// source t may have been written by the VALU just before, which needs two
+// wait states before a DPP read: hence the s_nop.
+template <int K>
+__device__ __forceinline__ void block_dot(float (&acc)[4], float t, const float* A) {
+  asm("s_nop 1\n"
+      "v_fmac_f32_dpp %0, %4, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %8 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %0, %4, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %10 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %11 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %12 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %0, %4, %13 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %15 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %0, %4, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %20 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])
+      : "v"(t), "v"(A[16 * K + 0]), "v"(A[16 * K + 1]), "v"(A[16 * K + 2]), "v"(A[16 * K + 3]),
+        "v"(A[16 * K + 4]), "v"(A[16 * K + 5]), "v"(A[16 * K + 6]), "v"(A[16 * K + 7]), "v"(A[16 * K + 8]),
+        "v"(A[16 * K + 9]), "v"(A[16 * K + 10]), "v"(A[16 * K + 11]), "v"(A[16 * K + 12]),
+        "v"(A[16 * K + 13]), "v"(A[16 * K + 14]), "v"(A[16 * K + 15]));
+}
+
+// Per-lane range of the finite entries of C' and the factored-form decision
+// (uniform: every valid lane must satisfy the bound).
+template <int NB>
+__device__ __forceinline__ bool factor_ok(const float (&C)[NB], float bbf, bool valid, float& cmin) {
+  float lo = __builtin_inff(), hi = -__builtin_inff();
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (C[j] < __builtin_inff()) {
+      lo = fminf(lo, C[j]);
+      hi = fmaxf(hi, C[j]);
+    }
+  }
+  cmin = lo < __builtin_inff() ? lo : 0.f;  // a lane without states: all factors 0, any finite cmin
+  return ballot(valid && !(bbf * (hi - lo) <= kSafeExp2)) == 0;
+}
+
+// C'(j) -> a_j = 2^(-bb (C'(j) - cmin)), 0 for the sentinel entries.
+template <int NB>
+__device__ __forceinline__ void to_factors(float (&C)[NB], float bbf, float cmin) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    C[j] = C[j] < __builtin_inff() ? exp2_fast(-bbf * (C[j] - cmin)) : 0.f;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+
+// log2 of sum over lanes of 2^l (l = -inf for empty lanes), float64.
+__device__ __forceinline__ double wave_lse2(double l) {
+  const double m = wave_max(l);
+  if (!(m > -__builtin_inf())) return m;
+  const double t = l > -__builtin_inf() ? exp2(l - m) : 0.0;
+  return m + log2(wave_sum(t));
 }
 
 __global__ void __launch_bounds__(kBlock) walk_exp_kernel(Views v, const float* beta) {
@@ -69,53 +153,104 @@ __global__ void __launch_bounds__(kBlock) walk_exp_kernel(Views v, const float* 
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     const InstU I = load_inst(v, b);
     if (I.status != 0) {
-      if (lane == 0) gp(v.part)[u] = 0.0;
+      if (lane == 0) gp(v.part)[u] = -__builtin_inf();
       continue;
     }
     const uint64_t local = u - (uint64_t)I.unit_begin;
     const bool valid = lane < (1 << I.L);
-    const uint64_t p = (local << I.L) | (uint64_t)lane;
     float C[kInnerStates];
     const double EP = lane_init<float, kInnerStates>(v, b, I, local, valid, myc, lane, C);
     const double bb = fabs((double)gp(beta)[b]) * kLog2e;
-    const double eref = load_gthr(v, b);
-    // beta = 0: a tiny negative slope keeps invalid table entries (+inf) at
-    // weight 0 without changing any valid weight (2^cst, cst = 0).
-    const float nb = bb > 0.0 ? (float)-bb : -1e-30f;
+    const float bbf = (float)bb;
     const uint32_t steps = 1u << I.no;
-    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(gp((const float*)v.tab) + I.tab_off * kInnerStates), (short)0,
-        (int)(steps * (uint32_t)(kInnerStates * sizeof(float))), 0x00020000);
-    const int qoff = (lane & 15) * 16;
     const gptr<const StepRec> rec = gp((const StepRec*)v.rec) + I.tab_off;
-    double K = EP;
-    double S = 0.0;
-    f32x4 tn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(trs, qoff, 0, 0));
-    double eon = rec[0].eo;
-    for (uint32_t t = 0; t < steps; ++t) {
-      const f32x4 tc = tn;
-      const double eoc = eon;
-      const uint32_t tt = t + 1 < steps ? t + 1 : t;
-      tn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(trs, qoff, (int)(tt * 256u), 0));
-      eon = rec[tt].eo;
-      if (t) {
-        const int l = __builtin_ctz(t);
-        K = __builtin_fma(((t >> (l + 1)) & 1) ? -1.0 : 1.0, myc[l * kWave + lane], K);
+    const int qoff = (lane & 15) * 16;
+    float cmin = 0.f;
+    const bool fac = v.factor && factor_ok(C, bbf, valid, cmin);
+    double K = EP;  // E_P + X_PO(p, g(t)): the lane's share of the step's constant
+    double r = 0.0, S = 0.0;
+    if (fac) {
+      to_factors(C, bbf, cmin);
+      const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(gp((const float*)v.etab) + I.tab_off * kInnerStates), (short)0,
+          (int)(steps * (uint32_t)(kInnerStates * sizeof(float))), 0x00020000);
+      const gptr<const double> tref = gp(v.tref) + I.tab_off;
+      const double cm = (double)cmin;
+      r = cm + tref[0] + K;
+      f32x4 bn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, qoff, 0, 0));
+      double trn = tref[0];
+      for (uint32_t t = 0; t < steps; ++t) {
+        const f32x4 bc = bn;
+        const double trc = trn;
+        const uint32_t tt = t + 1 < steps ? t + 1 : t;
+        bn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, qoff, (int)(tt * 256u), 0));
+        trn = tref[tt];
+        if (t) {
+          const int l = __builtin_ctz(t);
+          K = __builtin_fma(((t >> (l + 1)) & 1) ? -1.0 : 1.0, myc[l * kWave + lane], K);
+        }
+        const double lt = cm + trc + K;  // lower bound of the block's values
+        double ct = -bb * (lt - r);
+        if (ct > kRebase) {
+          S *= (double)exp2_fast((float)-ct);
+          r = lt;
+          ct = 0.0;
+        }
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        block_dot<0>(acc, bc.x, C);
+        block_dot<1>(acc, bc.y, C);
+        block_dot<2>(acc, bc.z, C);
+        block_dot<3>(acc, bc.w, C);
+        S = __builtin_fma((double)((acc[0] + acc[1]) + (acc[2] + acc[3])), (double)exp2_fast((float)ct), S);
       }
-      const float cst = (float)(-bb * (K + eoc - eref));
-      float acc[4] = {0.f, 0.f, 0.f, 0.f};
-      block_exp<0, 0>(acc, tc.x, C, nb, cst);
-      block_exp<1, 0>(acc, tc.y, C, nb, cst);
-      block_exp<2, 0>(acc, tc.z, C, nb, cst);
-      block_exp<3, 0>(acc, tc.w, C, nb, cst);
-      S += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    } else {
+      // beta = 0: a tiny negative slope keeps the sentinel entries (+inf) at
+      // weight 0 without changing any valid weight.
+      const float nb = bb > 0.0 ? -bbf : -1e-30f;
+      const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(gp((const float*)v.tab) + I.tab_off * kInnerStates), (short)0,
+          (int)(steps * (uint32_t)(kInnerStates * sizeof(float))), 0x00020000);
+      bool first = true;
+      f32x4 tn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(trs, qoff, 0, 0));
+      double eon = rec[0].eo;
+      for (uint32_t t = 0; t < steps; ++t) {
+        const f32x4 tc = tn;
+        const double eoc = eon;
+        const uint32_t tt = t + 1 < steps ? t + 1 : t;
+        tn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(trs, qoff, (int)(tt * 256u), 0));
+        eon = rec[tt].eo;
+        if (t) {
+          const int l = __builtin_ctz(t);
+          K = __builtin_fma(((t >> (l + 1)) & 1) ? -1.0 : 1.0, myc[l * kWave + lane], K);
+        }
+        float bm = __builtin_inff();
+        block_min<0, 0>(bm, tc.x, C);
+        block_min<1, 0>(bm, tc.y, C);
+        block_min<2, 0>(bm, tc.z, C);
+        block_min<3, 0>(bm, tc.w, C);
+        const double lt = (double)bm + K + eoc;
+        if (first || -bb * (lt - r) > kRebase) {
+          S = first ? 0.0 : S * (double)exp2_fast((float)(-bb * (r - lt)));
+          r = lt;
+          first = false;
+        }
+        const float cst = (float)(-bb * (K + eoc - r));
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        block_exp<0, 0>(acc, tc.x, C, nb, cst);
+        block_exp<1, 0>(acc, tc.y, C, nb, cst);
+        block_exp<2, 0>(acc, tc.z, C, nb, cst);
+        block_exp<3, 0>(acc, tc.w, C, nb, cst);
+        S += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+      }
     }
-    S = wave_sum(S);
-    if (lane == 0) gp(v.part)[u] = S;
+    // log2 of the lane's sum: log2 S - bb r
+    const double l = (valid && S > 0.0) ? log2(S) - bb * r : -__builtin_inf();
+    const double lu = wave_lse2(l);
+    if (lane == 0) gp(v.part)[u] = lu;
   }
 }
 
-// One thread per instance: S = sum over its units (in unit order), logZ.
+// One thread per instance: log-sum-exp of its units' log2 sums (in unit order).
 __global__ void finalize_logz_kernel(Views v, const float* beta, double* logz, int32_t* status) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= v.batch) return;
@@ -123,13 +258,43 @@ __global__ void finalize_logz_kernel(Views v, const float* beta, double* logz, i
   int32_t st = I->status;
   double out = __builtin_nan("");
   if (st == 0) {
+    const double* pu = v.part + I->unit_begin;
+    double m = -__builtin_inf();
+    for (int64_t u = 0; u < I->units; ++u) m = fmax(m, pu[u]);
     double S = 0.0;
-    for (int64_t u = 0; u < I->units; ++u) S += v.part[I->unit_begin + u];
-    const double eref = dec_key(v.gthr[b]);
-    out = -fabs((double)beta[b]) * eref + log(S);
+    for (int64_t u = 0; u < I->units; ++u) S += exp2(pu[u] - m);
+    out = (m + log2(S)) / kLog2e;
   }
   logz[b] = out;
   status[b] = st;
+}
+
+// Factor tables of the forward and adjoint walks: per step, b(t, j) =
+// 2^(-bb (T'(g(t); j) - min_j T')) in the layout of T', and
+// tref(t) = min_j T'(g(t); j) + E_O(g(t)).  One wave per step, lane = entry.
+__global__ void __launch_bounds__(256) prep_exp_tables_kernel(Views v, const float* beta, int inner) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t total = v.hdr->total_steps;
+  const int width = 1 << inner;
+  const float* tab = (const float*)v.tab;
+  float* etab = (float*)v.etab;
+  for (int64_t s = wave; s < total; s += nwaves) {
+    int lo = 0, hi = v.batch;  // instance of step s
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (v.inst[mid].tab_off <= s) lo = mid;
+      else hi = mid;
+    }
+    const float bbf = (float)(fabs((double)beta[lo]) * kLog2e);
+    const float tv = lane < width ? tab[s * width + lane] : __builtin_inff();
+    float m = tv;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
+    if (lane < width) etab[s * width + lane] = exp2_fast(-bbf * (tv - m));
+    if (lane == 0) v.tref[s] = (double)m + v.rec[s].eo;
+  }
 }
 
 // ------------------------------------------------------------ moment walk
@@ -139,6 +304,78 @@ __device__ __forceinline__ void block_w(float (&w)[kGradStates], float t, const 
   const float e = row_bcast<Q>(t) + C[16 * K + Q];
   w[16 * K + Q] = exp2_fast(__builtin_fmaf(e, nb, cst));
   if constexpr (Q + 1 < 16) block_w<K, Q + 1>(w, t, C, nb, cst);
+}
+
+// w(16K+Q) = b(16K+Q) * a(16K+Q) for Q = H*8 .. H*8+7, b broadcast from lane Q
+// of each 16-lane row (v_mul_f32 with a DPP row broadcast; written out because
+// the compiler leaves the broadcast as a separate move here).  s_nop: two wait
+// states between a VALU write of t and its DPP read.
+#define QBF_STR2(x) #x
+#define QBF_STR(x) QBF_STR2(x)
+template <int K, int H>
+__device__ __forceinline__ void block_prod8(float (&w)[kGradStates], float t, const float* A) {
+  constexpr int b0 = 16 * K + 8 * H;
+  if constexpr (H == 0) {
+#define QS0 "0"
+#define QS1 "1"
+#define QS2 "2"
+#define QS3 "3"
+#define QS4 "4"
+#define QS5 "5"
+#define QS6 "6"
+#define QS7 "7"
+    asm("s_nop 1\n"
+      "v_mul_f32_dpp %0, %8, %9 row_newbcast:" QS0 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %1, %8, %10 row_newbcast:" QS1 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %2, %8, %11 row_newbcast:" QS2 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %3, %8, %12 row_newbcast:" QS3 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %4, %8, %13 row_newbcast:" QS4 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %5, %8, %14 row_newbcast:" QS5 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %6, %8, %15 row_newbcast:" QS6 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %7, %8, %16 row_newbcast:" QS7 " row_mask:0xf bank_mask:0xf\n"
+        : "=&v"(w[b0]), "=&v"(w[b0 + 1]), "=&v"(w[b0 + 2]), "=&v"(w[b0 + 3]), "=&v"(w[b0 + 4]), "=&v"(w[b0 + 5]),
+          "=&v"(w[b0 + 6]), "=&v"(w[b0 + 7])
+        : "v"(t), "v"(A[b0]), "v"(A[b0 + 1]), "v"(A[b0 + 2]), "v"(A[b0 + 3]), "v"(A[b0 + 4]), "v"(A[b0 + 5]),
+          "v"(A[b0 + 6]), "v"(A[b0 + 7]));
+#undef QS0
+#undef QS1
+#undef QS2
+#undef QS3
+#undef QS4
+#undef QS5
+#undef QS6
+#undef QS7
+  } else {
+#define QS0 "8"
+#define QS1 "9"
+#define QS2 "10"
+#define QS3 "11"
+#define QS4 "12"
+#define QS5 "13"
+#define QS6 "14"
+#define QS7 "15"
+    asm("s_nop 1\n"
+      "v_mul_f32_dpp %0, %8, %9 row_newbcast:" QS0 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %1, %8, %10 row_newbcast:" QS1 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %2, %8, %11 row_newbcast:" QS2 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %3, %8, %12 row_newbcast:" QS3 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %4, %8, %13 row_newbcast:" QS4 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %5, %8, %14 row_newbcast:" QS5 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %6, %8, %15 row_newbcast:" QS6 " row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %7, %8, %16 row_newbcast:" QS7 " row_mask:0xf bank_mask:0xf\n"
+        : "=&v"(w[b0]), "=&v"(w[b0 + 1]), "=&v"(w[b0 + 2]), "=&v"(w[b0 + 3]), "=&v"(w[b0 + 4]), "=&v"(w[b0 + 5]),
+          "=&v"(w[b0 + 6]), "=&v"(w[b0 + 7])
+        : "v"(t), "v"(A[b0]), "v"(A[b0 + 1]), "v"(A[b0 + 2]), "v"(A[b0 + 3]), "v"(A[b0 + 4]), "v"(A[b0 + 5]),
+          "v"(A[b0 + 6]), "v"(A[b0 + 7]));
+#undef QS0
+#undef QS1
+#undef QS2
+#undef QS3
+#undef QS4
+#undef QS5
+#undef QS6
+#undef QS7
+  }
 }
 
 // s = sum_j w_j and v_a = sum_j w_j j_a (a < 5) by a pairwise tree.
@@ -168,7 +405,7 @@ __device__ __forceinline__ void block_moments(const float (&w)[kGradStates], flo
 
 __device__ __forceinline__ int pidx(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
-__global__ void __launch_bounds__(kBlock) walk_grad_kernel(Views v, const float* beta, const double* logz,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_grad_kernel(Views v, const float* beta, const double* logz,
                                                           int npairs) {
   __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
@@ -187,18 +424,25 @@ __global__ void __launch_bounds__(kBlock) walk_grad_kernel(Views v, const float*
     float C[kGradStates];
     const double EP = lane_init<float, kGradStates>(v, b, I, local, valid, myc, lane, C);
     const double bb = fabs((double)gp(beta)[b]) * kLog2e;
+    const float bbf = (float)bb;
     const double lz2 = uniform_f64(gp(logz)[b]) * kLog2e;
-    const float nb = bb > 0.0 ? (float)-bb : -1e-30f;  // see walk_exp_kernel
     const uint32_t steps = 1u << I.no;
-    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(gp((const float*)v.tab) + I.tab_off * kGradStates), (short)0,
-        (int)(steps * (uint32_t)(kGradStates * sizeof(float))), 0x00020000);
     const int qoff = (lane & 15) * 8;
     const gptr<const StepRec> rec = gp((const StepRec*)v.rec) + I.tab_off;
+    float cmin = 0.f;
+    const bool fac = v.factor && factor_ok(C, bbf, valid, cmin);
+    if (fac) to_factors(C, bbf, cmin);
+    // factored: b(t, j) rows and tref; direct: T' rows and E_O
+    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(gp((const float*)(fac ? v.etab : v.tab)) + I.tab_off * kGradStates), (short)0,
+        (int)(steps * (uint32_t)(kGradStates * sizeof(float))), 0x00020000);
+    const gptr<const double> tref = gp(v.tref) + I.tab_off;
 
     float W[kGradStates];
 #pragma unroll
     for (int j = 0; j < kGradStates; ++j) W[j] = 0.f;
+    // A[o][0] = sum_t x_o(t) s(t), A[o][1 + a] = sum_t x_o(t) v_a(t),
+    // Bo[hi (hi - 1) / 2 + lo] = sum_t x_lo(t) x_hi(t) s(t)
     float A[kGradMaxOuter][kGradInner + 1];
     float Bo[kGradMaxOuter * (kGradMaxOuter - 1) / 2];
 #pragma unroll
@@ -208,40 +452,189 @@ __global__ void __launch_bounds__(kBlock) walk_grad_kernel(Views v, const float*
 #pragma unroll
     for (int i = 0; i < kGradMaxOuter * (kGradMaxOuter - 1) / 2; ++i) Bo[i] = 0.f;
 
-    double K = EP;
-    f32x2 tn = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, 0, 0));
-    double eon = rec[0].eo;
-    for (uint32_t t = 0; t < steps; ++t) {
-      const f32x2 tc = tn;
-      const double eoc = eon;
-      const uint32_t tt = t + 1 < steps ? t + 1 : t;
-      tn = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, (int)(tt * 128u), 0));
-      eon = rec[tt].eo;
-      if (t) {
-        const int l = __builtin_ctz(t);
-        K = __builtin_fma(((t >> (l + 1)) & 1) ? -1.0 : 1.0, myc[l * kWave + lane], K);
-      }
-      const float cst = (float)(-bb * (K + eoc) - lz2);
+    double K = EP;  // E_P + X_PO(p, g(t)), moved along the walk
+    // Block sums of one step: y[0] = s = sum_j w(t, j), y[1 + a] = v_a =
+    // sum_j w(t, j) j_a; W[j] += w(t, j).  The caller has moved K to step t.
+    const double cm = (double)cmin;
+    const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_kernel
+    auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1]) {
       float w[kGradStates];
-      block_w<0, 0>(w, tc.x, C, nb, cst);
-      block_w<1, 0>(w, tc.y, C, nb, cst);
+      float va[kGradInner];
+      if constexpr (decltype(fc)::value) {
+        // sc = tref(t); weight = g * a_j * b(t, j) <= 1, g <= 2^kSafeExp2
+        const float g = exp2_fast((float)(-bb * (cm + sc + K) - lz2));
+        block_prod8<0, 0>(w, tc.x, C);
+        block_prod8<0, 1>(w, tc.x, C);
+        block_prod8<1, 0>(w, tc.y, C);
+        block_prod8<1, 1>(w, tc.y, C);
 #pragma unroll
-      for (int j = 0; j < kGradStates; ++j) W[j] += w[j];
-      float s, va[kGradInner];
-      block_moments(w, s, va);
-      const uint32_t o = (uint32_t)gray(t);
+        for (int j = 0; j < kGradStates; ++j) W[j] = __builtin_fmaf(g, w[j], W[j]);
+        block_moments(w, y[0], va);
+        y[0] *= g;
 #pragma unroll
-      for (int a = 0; a < kGradMaxOuter; ++a) {
-        if ((o >> a) & 1) {
-          A[a][0] += s;
+        for (int c = 0; c < kGradInner; ++c) y[1 + c] = va[c] * g;
+      } else {
+        // sc = E_O(g(t))
+        const float cst = (float)(-bb * (K + sc) - lz2);
+        block_w<0, 0>(w, tc.x, C, nb, cst);
+        block_w<1, 0>(w, tc.y, C, nb, cst);
 #pragma unroll
-          for (int c = 0; c < kGradInner; ++c) A[a][1 + c] += va[c];
+        for (int j = 0; j < kGradStates; ++j) W[j] += w[j];
+        block_moments(w, y[0], va);
 #pragma unroll
-          for (int a2 = a + 1; a2 < kGradMaxOuter; ++a2)
-            if ((o >> a2) & 1) Bo[a2 * (a2 - 1) / 2 + a] += s;
+        for (int c = 0; c < kGradInner; ++c) y[1 + c] = va[c];
+      }
+    };
+    const gptr<const double> scal = fac ? tref : gp((const double*)&rec[0].eo);
+    const int sstride = fac ? 1 : (int)(sizeof(StepRec) / sizeof(double));
+    f32x2 tn = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, 0, 0));
+    double sn = scal[0];
+    // operands of step t (clamped to the last step, loads unconditional)
+    auto fetch = [&](uint32_t t, f32x2& tv, double& sv) {
+      const uint32_t tt = t < steps ? t : steps - 1;
+      tv = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, (int)(tt * 128u), 0));
+      sv = scal[(int64_t)tt * sstride];
+    };
+    auto kflip = [&](int l, bool off) { K = __builtin_fma(off ? -1.0 : 1.0, myc[l * kWave + lane], K); };
+
+    auto walk = [&](auto fc) {
+      if (steps < 8) {
+        // short walks: every step adds into the moments of its set bits
+        for (uint32_t t = 0; t < steps; ++t) {
+          const f32x2 tc = tn;
+          const double sc = sn;
+          fetch(t + 1, tn, sn);
+          if (t) {
+            const int l = __builtin_ctz(t);
+            kflip(l, (t >> (l + 1)) & 1);
+          }
+          float y[kGradInner + 1];
+          block(fc, tc, sc, y);
+          const uint32_t o = (uint32_t)gray(t);
+  #pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            if ((o >> a) & 1) {
+  #pragma unroll
+              for (int c = 0; c <= kGradInner; ++c) A[a][c] += y[c];
+  #pragma unroll
+              for (int a2 = a + 1; a2 < 3; ++a2)
+                if ((o >> a2) & 1) Bo[a2 * (a2 - 1) / 2 + a] += y[0];
+            }
+          }
+        }
+      } else {
+        // Groups of 8 steps t = 8q + r.  Within a group, bit 0 of g(t) is set
+        // for r in {1,2,5,6} and bit 1 for r in {2,3,4,5}; bit 2 is set for
+        // r >= 4 (q even) or r < 4 (q odd), so it takes the half-group sums F
+        // (r < 4) and H (r >= 4); bits 3 and up equal those of g(q) and change
+        // only between groups, where bit 3 + CTZ(q) flips.  Moments of the high
+        // bits use on-intervals over groups: TG[c] sums the group totals y_c and
+        // TL[lo] the group sums of s over the steps with low bit lo set, over
+        // the groups before the current one; a high bit turning on opens
+        // (A -= TG, pairs -= TG / TL), turning off closes (+=).
+        float TG[kGradInner + 1], TL[3];
+  #pragma unroll
+        for (int c = 0; c <= kGradInner; ++c) TG[c] = 0.f;
+  #pragma unroll
+        for (int i = 0; i < 3; ++i) TL[i] = 0.f;
+        auto flip_high = [&](auto lc, float sgn, uint32_t gq) {
+          constexpr int l = decltype(lc)::value;  // 3 .. 7
+  #pragma unroll
+          for (int c = 0; c <= kGradInner; ++c) A[l][c] = __builtin_fmaf(sgn, TG[c], A[l][c]);
+  #pragma unroll
+          for (int h = 3; h < kGradMaxOuter; ++h) {
+            if (h == l) continue;
+            const int hi = h > l ? h : l, lo = h > l ? l : h;
+            const float m = ((gq >> (h - 3)) & 1) ? sgn : 0.f;
+            Bo[hi * (hi - 1) / 2 + lo] = __builtin_fmaf(m, TG[0], Bo[hi * (hi - 1) / 2 + lo]);
+          }
+  #pragma unroll
+          for (int lo = 0; lo < 3; ++lo) Bo[l * (l - 1) / 2 + lo] = __builtin_fmaf(sgn, TL[lo], Bo[l * (l - 1) / 2 + lo]);
+        };
+        const uint32_t groups = steps >> 3;
+        for (uint32_t q = 0; q < groups; ++q) {
+          const bool qodd = q & 1;
+          if (q) {
+            const int lq = __builtin_ctz(q), l = 3 + lq;
+            const bool off = (q >> (lq + 1)) & 1;
+            const float sgn = off ? 1.f : -1.f;
+            const uint32_t gq = (uint32_t)gray(q);
+            switch (l) {
+              case 3: flip_high(std::integral_constant<int, 3>{}, sgn, gq); break;
+              case 4: flip_high(std::integral_constant<int, 4>{}, sgn, gq); break;
+              case 5: flip_high(std::integral_constant<int, 5>{}, sgn, gq); break;
+              case 6: flip_high(std::integral_constant<int, 6>{}, sgn, gq); break;
+              default: flip_high(std::integral_constant<int, 7>{}, sgn, gq); break;
+            }
+          }
+          float F[kGradInner + 1], H[kGradInner + 1];
+  #pragma unroll
+          for (int c = 0; c <= kGradInner; ++c) F[c] = H[c] = 0.f;
+          float s0f = 0.f, s0h = 0.f, s1f = 0.f, s1h = 0.f;  // s over bit-0 / bit-1 steps per half
+  #pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const uint32_t t = 8 * q + r;
+            const f32x2 tc = tn;
+            const double sc = sn;
+            fetch(t + 1, tn, sn);
+            if (r == 0) {
+              if (q) kflip(3 + __builtin_ctz(q), (q >> (__builtin_ctz(q) + 1)) & 1);
+            } else if (r == 4) {
+              kflip(2, qodd);  // bit 2 turns off for odd q
+            } else {
+              const int l = (r & 1) ? 0 : 1;
+              kflip(l, r == 3 || r == 7 || r == 6);
+            }
+            float y[kGradInner + 1];
+            block(fc, tc, sc, y);
+            const bool b0 = r == 1 || r == 2 || r == 5 || r == 6;
+            const bool b1 = r >= 2 && r <= 5;
+  #pragma unroll
+            for (int c = 0; c <= kGradInner; ++c) {
+              if (b0) A[0][c] += y[c];
+              if (b1) A[1][c] += y[c];
+              if (r < 4) F[c] += y[c];
+              else H[c] += y[c];
+            }
+            if (b0 && b1) Bo[0] += y[0];
+            if (b0) {
+              if (r < 4) s0f += y[0];
+              else s0h += y[0];
+            }
+            if (b1) {
+              if (r < 4) s1f += y[0];
+              else s1h += y[0];
+            }
+          }
+          // bit 2 (set in the first half for odd q) and the group totals
+  #pragma unroll
+          for (int c = 0; c <= kGradInner; ++c) {
+            A[2][c] += qodd ? F[c] : H[c];
+            TG[c] += F[c] + H[c];
+          }
+          Bo[1] += qodd ? s0f : s0h;  // pair (0, 2)
+          Bo[2] += qodd ? s1f : s1h;  // pair (1, 2)
+          TL[0] += s0f + s0h;
+          TL[1] += s1f + s1h;
+          TL[2] += qodd ? F[0] : H[0];
+        }
+        // close the intervals of the high bits set in the last group
+        const uint32_t gl = (uint32_t)gray(groups - 1);
+  #pragma unroll
+        for (int h = 3; h < kGradMaxOuter; ++h) {
+          if (!((gl >> (h - 3)) & 1)) continue;
+  #pragma unroll
+          for (int c = 0; c <= kGradInner; ++c) A[h][c] += TG[c];
+  #pragma unroll
+          for (int lo = 0; lo < 3; ++lo) Bo[h * (h - 1) / 2 + lo] += TL[lo];
+  #pragma unroll
+          for (int h2 = h + 1; h2 < kGradMaxOuter; ++h2)
+            if ((gl >> (h2 - 3)) & 1) Bo[h2 * (h2 - 1) / 2 + h] += TG[0];
         }
       }
-    }
+    };
+    if (fac) walk(std::true_type{});
+    else walk(std::false_type{});
 
     // ---- assemble the unit's moments sum_x w x_i x_j (i <= j)
     const int n = I.n, B = I.B, no = I.no, pos0 = B + no;
@@ -343,16 +736,21 @@ __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta,
 
 }  // namespace
 
-hipError_t launch_walk_exp(const Views& v, const float* beta, const double* eref, int waves, hipStream_t s) {
-  (void)eref;
+hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,
+                                 hipStream_t s) {
+  int64_t waves = steps_bound < 1 ? 1 : steps_bound;
+  if (waves > 4096) waves = 4096;
+  hipLaunchKernelGGL(prep_exp_tables_kernel, dim3((int)((waves + 3) / 4)), dim3(256), 0, s, v, beta, inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_exp(const Views& v, const float* beta, int waves, hipStream_t s) {
   const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
   hipLaunchKernelGGL(walk_exp_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_logz(const Views& v, const float* beta, const double* eref, double* logz,
-                                int32_t* status, hipStream_t s) {
-  (void)eref;
+hipError_t launch_finalize_logz(const Views& v, const float* beta, double* logz, int32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(finalize_logz_kernel, dim3((v.batch + 255) / 256), dim3(256), 0, s, v, beta, logz, status);
   return hipGetLastError();
 }

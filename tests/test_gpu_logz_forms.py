@@ -1,0 +1,104 @@
+"""Both forms of the log-partition walks (factored: one FMA per state; direct:
+one exp2 per state) against the CPU oracle, and against each other.
+
+The factored form is taken per work unit when |beta| log2(e) times the
+lane's range of inner-table values is at most 84; large |beta| or large
+entries push units to the direct form, so the large-beta cases below run a
+mix of both.  logZ tolerance as in test_gpu_logz.py.  Gradient: a state's
+exponent carries up to about 3u |beta| sum|Q| of float32 rounding (u = 2^-24),
+which is also the relative error of its weight; at the large |beta| used here
+that term is added to the 1e-4 max-norm bound (at beta <= 4 and N(0, 1/n)
+entries it is below 4e-5).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2310_19373_amd import _lib, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def logz_tol(Q, beta):
+    return 2e-6 + 4e-7 * abs(beta) * float(np.abs(np.triu(Q.astype(np.float64))).sum())
+
+
+def grad_tol(Q, beta):
+    return 1e-4 + 2e-7 * abs(beta) * float(np.abs(np.triu(Q.astype(np.float64))).sum())
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def _run(Q, beta, factored: bool):
+    from paper_2310_19373_amd import api
+
+    old = _lib.get_tuning(_lib.TUNE_LOGZ_FACTORED)
+    _lib.set_tuning(_lib.TUNE_LOGZ_FACTORED, 1 if factored else -1)
+    try:
+        print(f"logz form={'factored' if factored else 'direct'} n={Q.shape[-1]} beta={beta}", flush=True)
+        Qt = torch.from_numpy(Q).cuda().requires_grad_(True)
+        bt = torch.tensor(float(beta), dtype=torch.float32, device="cuda", requires_grad=True)
+        lz = api.logz(Qt, bt)
+        lz.backward()
+        return float(lz), Qt.grad.cpu().numpy().astype(np.float64), float(bt.grad)
+    finally:
+        _lib.set_tuning(_lib.TUNE_LOGZ_FACTORED, old)
+
+
+CASES = [
+    (12, 1.0, "scaled"), (18, 4.0, "scaled"), (20, 0.5, "scaled"), (22, 1.0, "scaled"),
+    (16, 30.0, "unit"), (20, -25.0, "unit"), (22, 8.0, "unit"), (14, 3.0, "unit"),
+]
+
+
+@pytest.mark.parametrize("n,beta,kind", CASES)
+@pytest.mark.parametrize("factored", [True, False])
+def test_form_against_oracle(gpu_lib, n, beta, kind, factored):
+    scale = 1 / math.sqrt(n) if kind == "scaled" else 1.0
+    Q = inputs.random_f32(n, 900 + n, scale=scale)
+    lz, G, gb = _run(Q, beta, factored)
+    ref, mean = oracle.logz(Q, beta, with_mean=True)
+    assert abs(lz - ref) <= logz_tol(Q, beta), (lz, ref)
+    Gref = oracle.grad(Q, beta, ref)
+    assert _rel(G, Gref) <= grad_tol(Q, beta)
+    assert abs(gb + mean) <= grad_tol(Q, beta) * max(1.0, abs(mean))
+
+
+def test_forms_agree_on_mixed_batch(gpu_lib):
+    from paper_2310_19373_amd import api
+
+    rng = np.random.default_rng(31)
+    batch, nmax = 40, 20
+    ns = rng.integers(8, nmax + 1, batch).astype(np.int32)
+    Q = np.zeros((batch, nmax, nmax), dtype=np.float32)
+    betas = rng.choice([0.3, 2.0, 12.0, -20.0, 60.0], batch).astype(np.float32)
+    for b in range(batch):
+        n = int(ns[b])
+        Q[b, :n, :n] = np.triu(rng.standard_normal((n, n))).astype(np.float32)
+    out = {}
+    for factored in (True, False):
+        old = _lib.get_tuning(_lib.TUNE_LOGZ_FACTORED)
+        _lib.set_tuning(_lib.TUNE_LOGZ_FACTORED, 1 if factored else -1)
+        try:
+            Qt = torch.from_numpy(Q).cuda().requires_grad_(True)
+            lz = api.logz(Qt, torch.from_numpy(betas).cuda(), ns=torch.from_numpy(ns))
+            lz.sum().backward()
+            out[factored] = (lz.detach().cpu().numpy(), Qt.grad.cpu().numpy().astype(np.float64))
+        finally:
+            _lib.set_tuning(_lib.TUNE_LOGZ_FACTORED, old)
+    for b in range(batch):
+        n = int(ns[b])
+        Qb = np.ascontiguousarray(Q[b, :n, :n])
+        tol = logz_tol(Qb, float(betas[b]))
+        assert abs(out[True][0][b] - out[False][0][b]) <= 2 * tol, b
+        if b % 5 == 0:
+            ref = oracle.logz(Qb, float(betas[b]))
+            assert abs(out[True][0][b] - ref) <= tol, b
+            Gref = oracle.grad(Qb, float(betas[b]), ref)
+            assert _rel(out[True][1][b, :n, :n], Gref) <= grad_tol(Qb, float(betas[b])), b
+            assert _rel(out[False][1][b, :n, :n], Gref) <= grad_tol(Qb, float(betas[b])), b
