@@ -18,7 +18,7 @@
 //
 // where E_A is the objective restricted to the bits of group A and X_AB the
 // cross terms between groups A and B.  KE follows the Gray walk with the O(1)
-// update of Eq. 3 restricted to the prefix/outer cross terms; the inner bits
+// update of Eq. 2 (Sec. 2.1) restricted to the prefix/outer cross terms; the inner bits
 // are never walked, each inner state costs one table addition.
 #pragma once
 #include <hip/hip_runtime.h>

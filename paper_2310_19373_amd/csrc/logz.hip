@@ -142,7 +142,7 @@ __device__ __forceinline__ double wave_lse2(double l) {
   return m + log2(wave_sum(t));
 }
 
-__global__ void __launch_bounds__(kBlock) walk_exp_kernel(Views v, const float* beta) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_exp_kernel(Views v, const float* beta) {
   __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   double* myc = ctab[threadIdx.x >> 6];

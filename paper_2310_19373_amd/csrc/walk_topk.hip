@@ -10,7 +10,7 @@
 //   * outer walk over t = 0 .. 2^no - 1 in reflected Gray order: step t flips
 //     bit l = CTZ(t) (Sec. 2.2), turning it on iff bit l+1 of t is 0; the
 //     per-lane scalar KE = E_P + X_PO + E_O moves by +-c_l plus the uniform
-//     E_O(g(t)) (Eq. 3 restricted to the prefix/outer cross terms);
+//     E_O(g(t)) (the single-flip update of Eq. 2, Sec. 2.1, restricted to the prefix/outer cross terms);
 //   * 64 inner states per step: e_j = C'(j) + T'(g(t); j), with T' broadcast
 //     across each 16-lane row by DPP (one v_add_*_dpp per state) and folded by
 //     v_min3 (half an instruction per state);

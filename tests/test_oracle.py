@@ -49,7 +49,7 @@ def brute_topk(vals, k):
 
 
 def local_field(Q, x):
-    """h_l(x) = Q_ll + sum_{j != l} S_lj x_j, S = triu(Q,1) + triu(Q,1)^T (Eq. 3's bracket)."""
+    """h_l(x) = Q_ll + sum_{j != l} S_lj x_j, S = triu(Q,1) + triu(Q,1)^T (the bracket of Eq. 2)."""
     off = np.triu(Q, 1)
     S = off + off.T
     return np.diag(Q) + S @ x
@@ -95,8 +95,8 @@ def test_lower_triangle_is_ignored():
     assert np.array_equal(oracle.energies(Q, masks), oracle.energies(Qg, masks))
 
 
-def test_delta_rule_eq3():
-    # Eq. 3: flipping bit l changes f by s_l * (column-l sum + Q_ll + row-l sum),
+def test_delta_rule_eq2():
+    # Eq. 2: flipping bit l changes f by s_l * (column-l sum + Q_ll + row-l sum),
     # s_l = new - old bit; here via h_l(x).  Exact in integers for every x, l.
     n = 9
     Q = inputs.random_i32(n, 15)
@@ -245,7 +245,7 @@ def test_prefix_split_min_of_minima(m):
 
 
 def gray_walk_min(Q):
-    """Algorithm 1 in plain Python: flip bit CTZ(i), update v by Eq. 3 (strict <).
+    """Algorithm 1 in plain Python: flip bit CTZ(i), update v by Eq. 2 (strict <).
 
     Starts from x = 0 with v = v* = 0 (the code's initialisation, Sec. 3)."""
     n = Q.shape[0]

@@ -34,7 +34,7 @@ PINS = [
     pins.test_energy_equals_pair_sum_int,
     pins.test_energy_equals_pair_sum_float,
     pins.test_energy_equals_naive_xQx,
-    pins.test_delta_rule_eq3,
+    pins.test_delta_rule_eq2,
     pins.test_ties_go_to_lowest_natural_mask,
     pins.test_c_main_example_signed_reading,
     pins.test_diagonal_closed_form,
