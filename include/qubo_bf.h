@@ -154,6 +154,9 @@ const char* qubo_version(void);
  *   QUBO_TUNE_LOGZ_FACTORED       1: log-partition walks may use the factored
  *                                 form (one FMA per state); -1: always one exp
  *                                 per state (same results within rounding)
+ *   QUBO_TUNE_SEED_SWEEPS         descent passes of the per-instance threshold
+ *                                 seed before a top-k walk; -1: no seeding
+ *                                 (speed only: results are identical)
  * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)
  * set the initial values.  Returns QUBO_OK or QUBO_ERR_INVALID_ARG.
  */
@@ -166,7 +169,8 @@ enum {
   QUBO_TUNE_CHUNK_SINGLE = 6,
   QUBO_TUNE_CHUNK_BATCHED = 7,
   QUBO_TUNE_DYNAMIC_QUEUE = 8,
-  QUBO_TUNE_LOGZ_FACTORED = 9
+  QUBO_TUNE_LOGZ_FACTORED = 9,
+  QUBO_TUNE_SEED_SWEEPS = 10
 };
 int qubo_bf_set_tuning(int knob, int value);
 int qubo_bf_get_tuning(int knob);

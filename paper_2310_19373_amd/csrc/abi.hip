@@ -45,10 +45,11 @@ struct Tuning {
   int batched_outer = 8;
   int waves_per_cu = 12;
   int kprime = 0;
-  int chunk_single = 4;
+  int chunk_single = 2;
   int chunk_batched = 8;
   int dyn = 1;
   int logz_factored = 1;
+  int seed_sweeps = 2;
 };
 
 int env_int(const char* name, int dflt) {
@@ -69,6 +70,7 @@ Tuning& tuning() {
     d.chunk_batched = env_int("QUBO_BF_CHUNK_BATCHED", d.chunk_batched);
     d.dyn = env_int("QUBO_BF_DYNAMIC_QUEUE", d.dyn);
     d.logz_factored = env_int("QUBO_BF_LOGZ_FACTORED", d.logz_factored);
+    d.seed_sweeps = env_int("QUBO_BF_SEED_SWEEPS", d.seed_sweeps);
     return d;
   }();
   return t;
@@ -151,7 +153,7 @@ SplitH split_host(int n, const PlanParams& pp) {
 }
 
 struct Layout {
-  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, slots, part, lt, umap, etab, tref, total;
+  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, eod, eoi, slots, part, lt, umap, etab, tref, total;
   int64_t umap_cap;
 };
 
@@ -183,6 +185,10 @@ Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_u
   o += al(4 * (size_t)batch * steps * width);
   L.rec = o;
   o += al(sizeof(StepRec) * (size_t)batch * steps);
+  L.eod = o;
+  o += al(8 * (size_t)batch * steps);
+  L.eoi = o;
+  o += al(4 * (size_t)batch * steps);
   L.slots = o;
   o += al(sizeof(Slot) * (size_t)batch * slots * pp.kprime);
   L.part = o;
@@ -214,6 +220,8 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.ei = p + L.ei;
   v.tab = p + L.tab;
   v.rec = (StepRec*)(p + L.rec);
+  v.eod = (double*)(p + L.eod);
+  v.eoi = (int32_t*)(p + L.eoi);
   v.slots = (Slot*)(p + L.slots);
   v.part = (double*)(p + L.part);
   v.lt = p + L.lt;
@@ -222,6 +230,7 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.etab = L.etab ? (void*)(p + L.etab) : nullptr;
   v.tref = L.tref ? (double*)(p + L.tref) : nullptr;
   v.factor = L.etab && tuning().logz_factored > 0;
+  v.seed_sweeps = tuning().seed_sweeps;
   v.batch = batch;
   v.nmax = nmax;
   v.dyn = tuning().dyn != 0;
@@ -321,6 +330,7 @@ int qubo_bf_set_tuning(int knob, int value) {
     case QUBO_TUNE_CHUNK_BATCHED: t.chunk_batched = value > 0 ? value : d.chunk_batched; break;
     case QUBO_TUNE_DYNAMIC_QUEUE: t.dyn = value > 0 ? 1 : (value < 0 ? 0 : d.dyn); break;
     case QUBO_TUNE_LOGZ_FACTORED: t.logz_factored = value > 0 ? 1 : (value < 0 ? 0 : d.logz_factored); break;
+    case QUBO_TUNE_SEED_SWEEPS: t.seed_sweeps = value > 0 ? clampi(value, 1, 256) : (value < 0 ? 0 : d.seed_sweeps); break;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
   return QUBO_OK;
@@ -338,6 +348,7 @@ int qubo_bf_get_tuning(int knob) {
     case QUBO_TUNE_CHUNK_BATCHED: return t.chunk_batched;
     case QUBO_TUNE_DYNAMIC_QUEUE: return t.dyn;
     case QUBO_TUNE_LOGZ_FACTORED: return t.logz_factored;
+    case QUBO_TUNE_SEED_SWEEPS: return t.seed_sweeps;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
 }

@@ -68,16 +68,26 @@ struct Inst {
   double sign;              // +1, or -1 when the walk runs on -Q
 };
 
+// Work-queue segments: the unit range is cut into kXcds contiguous pieces, one
+// per XCD (the dispatcher places workgroup i on XCD i mod 8), so the waves of
+// one XCD walk neighbouring units -- mostly the same instances -- and their
+// step tables stay in that XCD's L2.  One counter per 128-byte line.
+constexpr int kXcds = 8;
+struct alignas(128) QueueSeg {
+  uint64_t next;  // next unit to hand out
+  uint64_t end;   // one past the segment's last unit
+};
+
 // Per-call header at the start of the workspace.
 struct Header {
-  uint64_t unit_counter;  // persistent work queue
   uint64_t total_units;
   int64_t total_steps;
   int64_t total_slots;
   int32_t batch;
   int32_t nmax;
   int32_t waves;          // waves of the persistent walk grid
-  int32_t chunk;          // consecutive work units per queue pull
+  int32_t chunk;          // largest run of work units per queue pull
+  QueueSeg seg[kXcds];    // persistent work queue
 };
 
 // Per-step uniform data of the outer walk.

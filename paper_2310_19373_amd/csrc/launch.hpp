@@ -18,6 +18,8 @@ struct Views {
   void* ei;        // [batch][64] double or int64
   void* tab;       // [total_steps][2^inner] float or int32, row-broadcast layout
   StepRec* rec;    // [total_steps]
+  double* eod;     // [total_steps] E_O(g(t)), dense (float path)
+  int32_t* eoi;    // [total_steps] -E_O(g(t)), dense (int path)
   Slot* slots;     // [total_slots][kprime]
   double* part;    // per-unit partial sums (logZ forward) / per-wave moments (gradient)
   void* lt;        // [batch][64][kLaneRec] lane table (double or int64), see prep_lanes
@@ -25,6 +27,7 @@ struct Views {
   void* etab;      // log-partition: factor table b(t, j), layout of tab (float), or null
   double* tref;    // log-partition: min_j T'(g(t); j) + E_O(g(t)) per step, or null
   int factor;      // log-partition: 1 = factored form allowed
+  int seed_sweeps; // descent passes of the threshold seed (0: no seeding)
   int64_t umap_cap;
   int batch, nmax;
   int dyn;         // 1: atomic work queue, 0: static round-robin of chunks

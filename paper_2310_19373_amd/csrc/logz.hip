@@ -163,7 +163,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
     const double bb = fabs((double)gp(beta)[b]) * kLog2e;
     const float bbf = (float)bb;
     const uint32_t steps = 1u << I.no;
-    const gptr<const StepRec> rec = gp((const StepRec*)v.rec) + I.tab_off;
     const int qoff = (lane & 15) * 16;
     float cmin = 0.f;
     const bool fac = v.factor && factor_ok(C, bbf, valid, cmin);
@@ -212,13 +211,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
           (int)(steps * (uint32_t)(kInnerStates * sizeof(float))), 0x00020000);
       bool first = true;
       f32x4 tn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(trs, qoff, 0, 0));
-      double eon = rec[0].eo;
+      const gptr<const double> eod = gp((const double*)v.eod) + I.tab_off;
+      double eon = eod[0];
       for (uint32_t t = 0; t < steps; ++t) {
         const f32x4 tc = tn;
         const double eoc = eon;
         const uint32_t tt = t + 1 < steps ? t + 1 : t;
         tn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(trs, qoff, (int)(tt * 256u), 0));
-        eon = rec[tt].eo;
+        eon = eod[tt];
         if (t) {
           const int l = __builtin_ctz(t);
           K = __builtin_fma(((t >> (l + 1)) & 1) ? -1.0 : 1.0, myc[l * kWave + lane], K);
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) prep_exp_tables_kernel(Views v, const flo
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
     if (lane < width) etab[s * width + lane] = exp2_fast(-bbf * (tv - m));
-    if (lane == 0) v.tref[s] = (double)m + v.rec[s].eo;
+    if (lane == 0) v.tref[s] = (double)m + v.eod[s];
   }
 }
 
@@ -428,7 +428,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     const double lz2 = uniform_f64(gp(logz)[b]) * kLog2e;
     const uint32_t steps = 1u << I.no;
     const int qoff = (lane & 15) * 8;
-    const gptr<const StepRec> rec = gp((const StepRec*)v.rec) + I.tab_off;
     float cmin = 0.f;
     const bool fac = v.factor && factor_ok(C, bbf, valid, cmin);
     if (fac) to_factors(C, bbf, cmin);
@@ -485,15 +484,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         for (int c = 0; c < kGradInner; ++c) y[1 + c] = va[c];
       }
     };
-    const gptr<const double> scal = fac ? tref : gp((const double*)&rec[0].eo);
-    const int sstride = fac ? 1 : (int)(sizeof(StepRec) / sizeof(double));
+    const gptr<const double> scal = fac ? tref : gp((const double*)v.eod) + I.tab_off;
     f32x2 tn = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, 0, 0));
     double sn = scal[0];
     // operands of step t (clamped to the last step, loads unconditional)
     auto fetch = [&](uint32_t t, f32x2& tv, double& sv) {
       const uint32_t tt = t < steps ? t : steps - 1;
       tv = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, (int)(tt * 128u), 0));
-      sv = scal[(int64_t)tt * sstride];
+      sv = scal[tt];
     };
     auto kflip = [&](int l, bool off) { K = __builtin_fma(off ? -1.0 : 1.0, myc[l * kWave + lane], K); };
 

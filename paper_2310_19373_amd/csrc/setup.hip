@@ -105,8 +105,12 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
     v.flushcnt[b] = 0;
   }
   if (tid == nt - 1) {
-    v.hdr->unit_counter = 0;
-    v.hdr->total_units = (uint64_t)su[nt - 1];
+    const uint64_t tu = (uint64_t)su[nt - 1];
+    for (int x = 0; x < kXcds; ++x) {
+      v.hdr->seg[x].next = tu * (uint64_t)x / kXcds;
+      v.hdr->seg[x].end = tu * (uint64_t)(x + 1) / kXcds;
+    }
+    v.hdr->total_units = tu;
     v.hdr->total_steps = ss[nt - 1];
     v.hdr->total_slots = sl[nt - 1];
     v.hdr->batch = batch;
@@ -121,7 +125,10 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
 
 // Rewinds the persistent work queue so a second walk can run over the same
 // plan (written by a kernel, not a memset, to stay graph-capture friendly).
-__global__ void reset_queue_kernel(Views v) { v.hdr->unit_counter = 0; }
+__global__ void reset_queue_kernel(Views v) {
+  const uint64_t tu = v.hdr->total_units;
+  for (int x = 0; x < kXcds; ++x) v.hdr->seg[x].next = tu * (uint64_t)x / kXcds;
+}
 
 template <class T>
 __device__ double absd(T x) {
@@ -263,21 +270,28 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   if (I->status != 0) return;
   const int n = I->n, kp = I->kprime, nm = v.nmax;
   if (kp > n + 1) return;
-  // the instance's n x n block, staged in LDS (row stride n)
+  // the instance's n x n block, staged in LDS (row stride n): exact copy for
+  // the final values, float32 copy for the descent
   W* qs = (W*)seed_lds;
+  float* qf = (float*)(seed_lds + sizeof(W) * (size_t)n * n);
   const W* qg = (const W*)v.qs + (int64_t)b * nm * nm;
-  for (int e = lane; e < n * n; e += kWave) qs[e] = qg[(int64_t)(e / n) * nm + e % n];
+  for (int e = lane; e < n * n; e += kWave) {
+    qs[e] = qg[(int64_t)(e / n) * nm + e % n];
+    qf[e] = (float)qs[e];
+  }
   __syncthreads();
   const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
   uint64_t x = lane == 0 ? 0 : (mix64(((uint64_t)b << 6) | (uint64_t)lane) & all);
-  // descent: every accepted flip lowers the value; at most 4n sweeps
-  for (int sweep = 0; sweep < 4 * n; ++sweep) {
+  // descent in float32 (any states back the bound, so neither convergence nor
+  // exact deltas matter here): at most `sweeps` passes over the bits
+  const int sweeps = v.seed_sweeps < 4 * n ? v.seed_sweeps : 4 * n;
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
     bool moved = false;
     for (int i = 0; i < n; ++i) {
-      W h = qs[i * n + i];
+      float h = qf[i * n + i];
       for (int j = 0; j < n; ++j)
-        if (j != i && ((x >> j) & 1)) h += qs[i * n + j];
-      const W d = ((x >> i) & 1) ? -h : h;
+        if (j != i && ((x >> j) & 1)) h += qf[i * n + j];
+      const float d = ((x >> i) & 1) ? -h : h;
       if (d < 0) {
         x ^= 1ull << i;
         moved = true;
@@ -352,6 +366,8 @@ __global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
             if (u < B) H[u] += qs[(int64_t)u * v.nmax + a];
         }
       }
+      v.eod[s] = (double)eo;
+      v.eoi[s] = (int32_t)(-eo);
       StepRec* r = &v.rec[s];
       r->eo = (double)eo;
 #pragma unroll
@@ -408,7 +424,9 @@ hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s) {
 }
 
 hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)v.nmax * (size_t)v.nmax;  // both paths hold 8-byte entries
+  if (v.seed_sweeps <= 0) return hipSuccess;  // seeding switched off
+  // 8-byte exact entries (both paths) + a float32 copy
+  const size_t lds = (sizeof(double) + sizeof(float)) * (size_t)v.nmax * (size_t)v.nmax;
   if (is_int)
     hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), lds, s, v);
   else

@@ -53,43 +53,70 @@ __device__ __forceinline__ int find_unit(const Views& v, uint64_t u) {
   return lo;
 }
 
-// Next work unit of the persistent queue, identical in all lanes.  Every lane
-// issues the atomic (increment 1 from lane 0, 0 from the others) and the
-// result of the first lane is broadcast: there is no lane-divergent branch
-// around the pull, so the loop exit it controls is uniform.  Must be called
-// with all lanes active.
-__device__ __forceinline__ uint64_t next_unit(const Views& v, int lane) {
-  const uint64_t r = atomicAdd((unsigned long long*)&v.hdr->unit_counter, lane == 0 ? 1ull : 0ull);
+// Takes `want` units from queue segment `sg` and returns the first, identical
+// in all lanes.  Every lane issues the atomic (increment `want` from lane 0, 0
+// from the others) and the result of the first lane is broadcast: there is no
+// lane-divergent branch around the pull, so the loop exit it controls is
+// uniform.  Must be called with all lanes active and a uniform `want`.
+__device__ __forceinline__ uint64_t take_units(const Views& v, int sg, int lane, uint64_t want) {
+  const uint64_t r = atomicAdd((unsigned long long*)&v.hdr->seg[sg].next, lane == 0 ? want : 0ull);
   return uniform_u64(r);
 }
 
-// Work distribution of the persistent walks: chunks of consecutive
-// units, taken from the atomic queue (v.dyn) or statically (wave w of G takes
-// chunks w, w+G, ...).  Consecutive units of a chunk mostly belong to one
-// instance, so a wave's candidate list carries over between them.
+// Work distribution of the persistent walks, in runs of consecutive units.
+// Dynamic (v.dyn): a wave starts on the queue segment of its XCD (workgroup
+// index mod kXcds) and, once that is empty, moves on to the following
+// segments only, so its units increase monotonically.  Within a segment,
+// guided self-scheduling: a pull takes min(cap, rest / (2 x waves per
+// segment)) units (at least 1), rest being what the segment had left after
+// the wave's previous pull, so runs shrink towards the end.  Static: wave w
+// of G takes runs w, w+G, ... of cap units.  Either way a wave meets each
+// instance in one contiguous stretch, and its candidate list carries over
+// between the units of a run.
 struct WorkIter {
-  uint64_t total, chunk, u = 0, u_end = 0, next_static;
+  uint64_t total, cap, want, waves2, u = 0, u_end = 0, next_static, seg_end;
   int64_t stride;
+  int sg;
   bool dyn;
   __device__ WorkIter(const Views& v, uint64_t total_units) {
     total = total_units;
-    chunk = (uint64_t)(uint32_t)uniform_i32(gp((const Header*)v.hdr)->chunk);
+    cap = (uint64_t)(uint32_t)uniform_i32(gp((const Header*)v.hdr)->chunk);
+    want = cap;
     dyn = v.dyn != 0;
     next_static = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const uint64_t per_seg = (uint64_t)stride / kXcds;
+    waves2 = 2 * (per_seg > 0 ? per_seg : 1);
+    sg = (int)(blockIdx.x % kXcds);
+    seg_end = uniform_u64(gp((const Header*)v.hdr)->seg[sg].end);
   }
   __device__ __forceinline__ bool next(const Views& v, int lane, uint64_t& unit) {
     if (u >= u_end) {
-      uint64_t c;
       if (dyn) {
-        c = next_unit(v, lane);
+        for (;;) {  // at most kXcds segments; every value here is wave-uniform
+          const int s = uniform_i32(sg);
+          const uint64_t w = uniform_u64(want);
+          const uint64_t e = uniform_u64(seg_end);
+          const uint64_t c = take_units(v, s, lane, w);
+          if (c < e) {
+            u = c;
+            u_end = c + w < e ? c + w : e;
+            const uint64_t share = (e - u_end) / waves2;
+            want = share < 1 ? 1 : (share > cap ? cap : share);
+            break;
+          }
+          sg = s + 1;
+          if (sg >= kXcds) return false;
+          seg_end = uniform_u64(gp((const Header*)v.hdr)->seg[sg].end);
+          want = cap;
+        }
       } else {
-        c = next_static;
+        const uint64_t c = next_static;
         next_static += (uint64_t)stride;
+        u = c * cap;
+        if (u >= total) return false;
+        u_end = u + cap < total ? u + cap : total;
       }
-      u = c * chunk;
-      if (u >= total) return false;
-      u_end = u + chunk < total ? u + chunk : total;
     }
     unit = u++;
     return true;

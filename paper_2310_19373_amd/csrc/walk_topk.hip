@@ -121,7 +121,8 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
       (void*)(gp((const E*)v.tab) + I.tab_off * kInnerStates), (short)0,
       (int)(steps * (uint32_t)(kInnerStates * sizeof(E))), 0x00020000);
   const int qoff = (lane & 15) * 16;
-  const gptr<const StepRec> rec = gp((const StepRec*)v.rec) + I.tab_off;
+  const gptr<const double> eod = gp((const double*)v.eod) + I.tab_off;
+  const gptr<const int32_t> eoi = gp((const int32_t*)v.eoi) + I.tab_off;
   const W c0 = I.no > 0 ? myc[lane] : (W)0;
   const W c1 = I.no > 1 ? myc[kWave + lane] : (W)0;
   const W c2 = I.no > 2 ? myc[2 * kWave + lane] : (W)0;
@@ -137,8 +138,8 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
     Ops o;
     o.tv = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(
                                      trs, qoff, (int)(tt * (uint32_t)(kInnerStates * sizeof(E))), 0));
-    if constexpr (std::is_same_v<E, float>) o.eo = rec[tt].eo;
-    else o.eo = rec[tt].neo;
+    if constexpr (std::is_same_v<E, float>) o.eo = eod[tt];
+    else o.eo = eoi[tt];
     return o;
   };
   // Threshold refresh: fold an improvement of thr into Dp.
