@@ -35,7 +35,7 @@ def _gpu_logz_grad(Q, beta):
     bt = torch.tensor(float(beta), dtype=torch.float32, device="cuda", requires_grad=True)
     lz = api.logz(Qt, bt)
     lz.backward()
-    return float(lz), Qt.grad.cpu().numpy().astype(np.float64), float(bt.grad)
+    return float(lz.detach()), Qt.grad.cpu().numpy().astype(np.float64), float(bt.grad)
 
 
 def _rel(a, b):

@@ -45,7 +45,7 @@ def _run(Q, beta, factored: bool):
         bt = torch.tensor(float(beta), dtype=torch.float32, device="cuda", requires_grad=True)
         lz = api.logz(Qt, bt)
         lz.backward()
-        return float(lz), Qt.grad.cpu().numpy().astype(np.float64), float(bt.grad)
+        return float(lz.detach()), Qt.grad.cpu().numpy().astype(np.float64), float(bt.grad)
     finally:
         _lib.set_tuning(_lib.TUNE_LOGZ_FACTORED, old)
 
