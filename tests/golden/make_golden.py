@@ -69,10 +69,23 @@ def single_n40_f32_planted():
         lo = int(p) << 22
         E, M = oracle.topk(Q, 8, lo=lo, hi=lo + (1 << 22))
         ranges.append({"lo": lo, "hi": lo + (1 << 22), "energies": _energies(E), "masks": [int(m) for m in M]})
+    t_random = time.time() - t
+    # Ranges where the lowest states live: the aligned block of 2^22 masks that
+    # holds the planted minimiser, and the blocks holding it with one of the
+    # top 18 bits flipped (x* comes from the generator, not from any solve).
+    near = []
+    t = time.time()
+    for h in [None] + list(range(22, 40)):
+        x = int(xstar) if h is None else int(xstar) ^ (1 << h)
+        lo = (x >> 22) << 22
+        E, M = oracle.topk(Q, 16, lo=lo, hi=lo + (1 << 22))
+        near.append({"lo": lo, "hi": lo + (1 << 22), "flipped_bit": h, "energies": _energies(E),
+                     "masks": [int(m) for m in M]})
     _dump("single_n40_f32_planted", {
         "workload": "n=40 float32 N(0,1/n) + planted minimiser, seed 2",
         "xstar": int(xstar), "energy_xstar": float(e), "threads": oracle.max_threads(),
-        "ranges_seconds": time.time() - t, "ranges": ranges})
+        "ranges_seconds": t_random, "ranges": ranges,
+        "near_ranges_k": 16, "near_ranges_seconds": time.time() - t, "near_ranges": near})
 
 
 def logz_sample():

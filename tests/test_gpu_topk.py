@@ -90,6 +90,23 @@ def test_single_n40_planted(gpu_lib):
         for E, M in zip(r["energies"], r["masks"]):
             if E < e[-1] or (E == e[-1] and M < int(m[-1])):
                 assert M in got, (r["lo"], E, M)
+    # ranges around the planted minimiser, where the lowest states live: the
+    # oracle's 16 best of a range contain every globally-top-16 state of that
+    # range, so (a) each returned mask inside a range is in the range's list
+    # with the same energy, and (b) each state of the range's list that ranks
+    # before the 16th returned state is returned.
+    ret = {int(x): float(y) for x, y in zip(m, e)}
+    seen = 0
+    for r in g["near_ranges"]:
+        lst = dict(zip(r["masks"], r["energies"]))
+        for M, E in ret.items():
+            if r["lo"] <= M < r["hi"]:
+                seen += 1
+                assert M in lst and lst[M] == E, (r["lo"], M, E)
+        for E, M in zip(r["energies"], r["masks"]):
+            if E < e[-1] or (E == e[-1] and M < int(m[-1])):
+                assert M in got, (r["lo"], E, M)
+    assert seen >= 2, "the near ranges hold too few of the returned states to test"
 
 
 @pytest.mark.parametrize("dtype", ["f32", "i32"])
