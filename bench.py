@@ -98,7 +98,43 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def extra_batched(dev, plain_loop=True):
+def extra_single(dev, name, Q, k, dt, reps):
+    """One full qubo_bf_solve per call on a smaller configuration; states/s of
+    the call and the walk kernel's VALU roofline fraction (1.5 lane-ops per
+    state, HIP events around the walk launch)."""
+    import torch
+
+    from paper_2310_19373_amd import _lib
+
+    n = Q.shape[0]
+    Qd = torch.from_numpy(Q).to(dev)
+    L = _lib.lib()
+    ws_bytes = L.qubo_bf_workspace_size(n, k, dt)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=dev)
+    mk = torch.empty(k, dtype=torch.int64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def call():
+        _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, n, dt, k, en.data_ptr(), mk.data_ptr(), st.data_ptr(),
+                                   ws.data_ptr(), ws_bytes, stream))
+
+    call()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    _lib.prof_enable(True)
+    _lib.prof_collect("walk_topk")
+    t = _time(call, reps)
+    _lib.prof_enable(False)
+    wms, wn = _lib.prof_collect("walk_topk")
+    states = float(1 << n)
+    walk_s = wms / 1e3 / max(wn, 1)
+    return {"workload": name, "states": states, "ms_per_call": t * 1e3, "states_per_s": states / t,
+            "walk_ms": walk_s * 1e3, "walk_frac": states * ALG_OPS_PER_STATE / walk_s / PEAK_LANE_OPS}
+
+
+def extra_batched(dev, plain_loop=True, tune=True):
     """Config 4: 4096 QUBOs, n uniform in [12, 28], k=1 -- one captured graph
     replay vs one qubo_bf_solve call per instance on the same stream."""
     import torch
@@ -112,7 +148,7 @@ def extra_batched(dev, plain_loop=True):
     names = list(autotune.BATCHED_SPACE)
     with autotune.keep_tuning(names):
         # the launch shape is picked by the autotuner on this batch
-        tune = autotune.tune_batched(Q, ns, k=1, reps=3)
+        res = autotune.tune_batched(Q, ns, k=1, reps=3) if tune else None
         solver = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=True)
         solver.load(Q, ns)
         solver.run()
@@ -153,8 +189,9 @@ def extra_batched(dev, plain_loop=True):
     return {"workload": "4096 QUBOs, n uniform in [12,28] (seed 3), float32 N(0,1), k=1",
             "states": states, "batched_ms": t_batched * 1e3, "batched_states_per_s": states / t_batched,
             "walk_ms": wms / max(wn, 1), "plain_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched,
-            "identical_to_plain": same, "tuned": tune.best, "untuned_ms": tune.start_ms,
-            "tune_trials": len(tune.trials)}
+            "identical_to_plain": same,
+            "tuned": res.best if res else autotune.current(names), "untuned_ms": res.start_ms if res else None,
+            "tune_trials": len(res.trials) if res else 0}
 
 
 def extra_logz(dev, plain_loop=True):
@@ -210,6 +247,8 @@ def main():
                     help="also time the batched and log-partition workloads against one call per instance")
     ap.add_argument("--only", choices=("batched", "logz"),
                     help="run only that secondary workload, without the one-call-per-instance loop")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched workload: keep the current launch shape (knobs or QUBO_BF_* variables) untuned")
     ap.add_argument("--sources-sha", action="store_true", help="print the walk sources' sha256 and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration for HBM bytes)")
@@ -238,8 +277,11 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}), flush=True)
         return
     if args.only:
-        leg = extra_batched if args.only == "batched" else extra_logz
-        print(json.dumps({args.only: leg(dev, plain_loop=False)}), flush=True)
+        if args.only == "batched":
+            res = extra_batched(dev, plain_loop=False, tune=not args.no_tune)
+        else:
+            res = extra_logz(dev, plain_loop=False)
+        print(json.dumps({args.only: res}), flush=True)
         return
     Q, xstar = inputs.single_n40_f32_planted()
     n, k = 40, 16
@@ -302,7 +344,12 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, n, k)
     if args.extra:
-        out["extra"] = {"batched": extra_batched(dev), "logz": extra_logz(dev)}
+        out["extra"] = {
+            "single_n20_f32": extra_single(dev, "n=20 float32 N(0,1) (seed 0), k=8", inputs.single_n20_f32(), 8,
+                                           _lib.QUBO_F32, 50),
+            "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
+                                           inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10),
+            "batched": extra_batched(dev), "logz": extra_logz(dev)}
     print(json.dumps(out), flush=True)
 
 

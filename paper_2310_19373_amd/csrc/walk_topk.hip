@@ -33,7 +33,16 @@ namespace {
 // Writes the wave's list to the next free slot of instance b.  A count above
 // the slot capacity is reported by the finalize kernel (it cannot happen: a
 // wave flushes an instance at most once per contiguous run of its units).
+//
+// A list whose best entry lies above the instance's published threshold is
+// dropped: the threshold only decreases and is backed by K' real states, so
+// each of the instance's K' best states has a key at most the final
+// threshold and sits, by then, in the list of the wave that walked it --
+// whose best entry is therefore at most the threshold, and that list is
+// flushed.  Dropping the others spares one slot-counter atomic per wave per
+// instance (thousands on one address for a single instance).
 __device__ void flush(const Views& v, int b, double lkey, uint64_t lmask, int lane) {
+  if (!(readlane_f64(lkey, 0) <= load_gthr(v, b))) return;  // uniform
   const InstU I = load_inst(v, b);
   const uint32_t slot = (uint32_t)uniform_i32((int)atomicAdd(v.flushcnt + b, lane == 0 ? 1u : 0u));
   if ((int64_t)slot < I.slot_cap && lane < I.kp) {
