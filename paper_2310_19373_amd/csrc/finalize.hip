@@ -27,13 +27,13 @@ template <>
 struct Rescore<float> {
   using En = double;
   __device__ static En sentinel() { return __builtin_inf(); }
-  __device__ static En energy(const float* Q, int64_t ldq, int n, uint64_t m) {
+  __device__ static En energy(const float* Q, int ldq, int n, uint64_t m) {
     double tot = 0.0;
     for (int i = 0; i < n; ++i) {
       if (!((m >> i) & 1)) continue;
-      double row = (double)Q[(int64_t)i * ldq + i];
+      double row = (double)Q[i * ldq + i];
       for (int j = i + 1; j < n; ++j)
-        if ((m >> j) & 1) row = __dadd_rn(row, (double)Q[(int64_t)i * ldq + j]);
+        if ((m >> j) & 1) row = __dadd_rn(row, (double)Q[i * ldq + j]);
       tot = __dadd_rn(tot, row);
     }
     return tot;
@@ -43,13 +43,13 @@ template <>
 struct Rescore<int32_t> {
   using En = int64_t;
   __device__ static En sentinel() { return INT64_MAX; }
-  __device__ static En energy(const int32_t* Q, int64_t ldq, int n, uint64_t m) {
+  __device__ static En energy(const int32_t* Q, int ldq, int n, uint64_t m) {
     int64_t tot = 0;
     for (int i = 0; i < n; ++i) {
       if (!((m >> i) & 1)) continue;
-      int64_t row = Q[(int64_t)i * ldq + i];
+      int64_t row = Q[i * ldq + i];
       for (int j = i + 1; j < n; ++j)
-        if ((m >> j) & 1) row += Q[(int64_t)i * ldq + j];
+        if ((m >> j) & 1) row += Q[i * ldq + j];
       tot += row;
     }
     return tot;
@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   using En = typename Rescore<Qin>::En;
   __shared__ double sk[kMaxFinWaves][kWave];
   __shared__ uint64_t sm[kMaxFinWaves][kWave];
+  __shared__ Qin sq[64 * 64];  // the instance's n x n block, row stride n
   const int b = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const Inst* I = &v.inst[b];
@@ -102,6 +103,11 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   }
   sk[w][lane] = lkey;
   sm[w][lane] = lmask;
+  if (st0 == 0) {
+    const int n = I->n;
+    const Qin* Qb = q + (int64_t)b * stride;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) sq[e] = Qb[(int64_t)(e / n) * ldq + e % n];
+  }
   __syncthreads();
   if (w != 0) return;
   for (int o = 1; o < nw; ++o) {
@@ -119,7 +125,7 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   uint64_t m = ~0ull;
   if (st0 == 0 && lane < kp && lkey < __builtin_inf()) {
     m = lmask;
-    en = Rescore<Qin>::energy(q + (int64_t)b * stride, ldq, I->n, m);
+    en = Rescore<Qin>::energy(sq, I->n, I->n, m);
   }
   wave_sort(en, m, lane);
   if constexpr (std::is_same_v<Qin, float>) {

@@ -234,20 +234,6 @@ __global__ void __launch_bounds__(64) prep_lanes_kernel(Views v) {
   for (int i = 0; i < kLaneRec; ++i) lt[i] = rec[i];
 }
 
-// Exact value of state x from the (sign-applied) symmetric copy of Q.
-template <class W>
-__device__ W state_energy(const W* qs, int nm, int n, uint64_t x) {
-  W e = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!((x >> i) & 1)) continue;
-    W row = qs[(int64_t)i * nm + i];
-    for (int j = i + 1; j < n; ++j)
-      if ((x >> j) & 1) row += qs[(int64_t)i * nm + j];
-    e += row;
-  }
-  return e;
-}
-
 // SplitMix64 output function (Steele, Lea, Flood 2014), used as a hash.
 __device__ uint64_t mix64(uint64_t z) {
   z += 0x9e3779b97f4a7c15ull;
@@ -256,12 +242,30 @@ __device__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// Local field h_i(x) = sum_{j != i} S_ij x_j of row i (zero diagonal, row
+// stride np, zero padding), four independent partial sums.
+template <class T>
+__device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
+  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int j = 0; j < np; j += 4) {
+    a0 += ((x >> j) & 1) ? row[j] : (T)0;
+    a1 += ((x >> (j + 1)) & 1) ? row[j + 1] : (T)0;
+    a2 += ((x >> (j + 2)) & 1) ? row[j + 2] : (T)0;
+    a3 += ((x >> (j + 3)) & 1) ? row[j + 3] : (T)0;
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
 // A-priori threshold for instance b.  Each lane runs a greedy one-flip descent
 // from its own start (lane 0 from x = 0); the best local minimum x* and its n
 // one-flip neighbours are n + 1 distinct states, so the K'-th smallest of their
 // values bounds the instance's K'-th smallest value from above.  Published with
 // the float filter's error margin, the bound discards nothing the walk would
 // keep; it only spares each wave the replays of its cold start.
+//
+// With S the symmetric off-diagonal part and d the diagonal,
+//   f(x) = sum_i x_i (d_i + h_i(x) / 2),  f(x ^ e_i) = f(x) + (1 - 2 x_i)(d_i + h_i(x)),
+// so lane i evaluates one field of x* and the wave sums: O(n) per lane.
 template <class W>
 __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   extern __shared__ unsigned char seed_lds[];
@@ -270,14 +274,22 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   if (I->status != 0) return;
   const int n = I->n, kp = I->kprime, nm = v.nmax;
   if (kp > n + 1) return;
-  // the instance's n x n block, staged in LDS (row stride n): exact copy for
-  // the final values, float32 copy for the descent
-  W* qs = (W*)seed_lds;
-  float* qf = (float*)(seed_lds + sizeof(W) * (size_t)n * n);
+  const int np = (n + 3) & ~3;
+  // exact (W) and float32 copies of S with zero diagonal and padded rows, and d
+  W* sw = (W*)seed_lds;
+  W* dw = sw + np * np;
+  float* sf = (float*)(dw + np);
+  float* df = sf + np * np;
   const W* qg = (const W*)v.qs + (int64_t)b * nm * nm;
-  for (int e = lane; e < n * n; e += kWave) {
-    qs[e] = qg[(int64_t)(e / n) * nm + e % n];
-    qf[e] = (float)qs[e];
+  for (int e = lane; e < np * np; e += kWave) {
+    const int i = e / np, j = e % np;
+    const W q = (i < n && j < n && i != j) ? qg[(int64_t)i * nm + j] : (W)0;
+    sw[e] = q;
+    sf[e] = (float)q;
+  }
+  for (int i = lane; i < np; i += kWave) {
+    dw[i] = i < n ? qg[(int64_t)i * nm + i] : (W)0;
+    df[i] = (float)dw[i];
   }
   __syncthreads();
   const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
@@ -288,28 +300,41 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     bool moved = false;
     for (int i = 0; i < n; ++i) {
-      float h = qf[i * n + i];
-      for (int j = 0; j < n; ++j)
-        if (j != i && ((x >> j) & 1)) h += qf[i * n + j];
-      const float d = ((x >> i) & 1) ? -h : h;
-      if (d < 0) {
+      const float g = df[i] + field(sf + i * np, np, x);
+      if ((((x >> i) & 1) ? -g : g) < 0.f) {
         x ^= 1ull << i;
         moved = true;
       }
     }
     if (!moved) break;
   }
-  // best local minimum over the wave, ties to the lower lane
-  double key = (double)state_energy(qs, n, n, x);
+  // best local minimum over the wave by its float32 value, ties to the lower lane
+  float fx = 0.f;
+  for (int i = 0; i < n; ++i)
+    if ((x >> i) & 1) fx += df[i] + 0.5f * field(sf + i * np, np, x);
+  double key = (double)fx;
   uint64_t mask = x;
   wave_sort(key, mask, lane);
   const uint64_t xs = readlane_u64(mask, 0);
-  // lane i < n: neighbour x* ^ e_i; lane n: x* itself
+  // exact values: lane i < n evaluates field i of x*
+  W gi = 0, term = 0;
+  if (lane < n) {
+    gi = dw[lane] + field(sw + lane * np, np, xs);  // d_i + h_i(x*)
+    if ((xs >> lane) & 1) term = dw[lane] + gi;      // 2 x_i (d_i + h_i / 2)
+  }
+  W tot = term;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+  if constexpr (std::is_same_v<W, double>) tot = uniform_f64(tot) * 0.5;
+  else tot = (W)uniform_u64((uint64_t)tot) / 2;  // even: 2 sum_i x_i d_i + 2 sum_{i<j} S_ij x_i x_j
   key = __builtin_inf();
   mask = ~0ull;
-  if (lane <= n) {
-    mask = lane < n ? (xs ^ (1ull << lane)) : xs;
-    key = (double)state_energy(qs, n, n, mask);
+  if (lane < n) {
+    mask = xs ^ (1ull << lane);
+    key = (double)(((xs >> lane) & 1) ? tot - gi : tot + gi);
+  } else if (lane == n) {
+    mask = xs;
+    key = (double)tot;
   }
   wave_sort(key, mask, lane);
   const double vk = readlane_f64(key, kp - 1);
@@ -425,8 +450,9 @@ hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s) {
 
 hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s) {
   if (v.seed_sweeps <= 0) return hipSuccess;  // seeding switched off
-  // 8-byte exact entries (both paths) + a float32 copy
-  const size_t lds = (sizeof(double) + sizeof(float)) * (size_t)v.nmax * (size_t)v.nmax;
+  // padded n x n plus the diagonal, 8-byte exact entries (both paths) and a float32 copy
+  const size_t np = (size_t)((v.nmax + 3) & ~3);
+  const size_t lds = (sizeof(double) + sizeof(float)) * (np * np + np);
   if (is_int)
     hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), lds, s, v);
   else

@@ -120,7 +120,11 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   // the filter of step t is  min_j e_j <= Dp - E_O(g(t)).  A threshold change by
   // delta moves Dp by delta.
   using Acc = std::conditional_t<std::is_same_v<E, float>, double, int32_t>;
-  double thr = fmin(fmin(load_gthr(v, b), I.big), readlane_f64(lkey, I.kp - 1));
+  // pub also tracks the lowest threshold seen, so a wave publishes (one
+  // atomic) only a value below what the instance already has
+  const double g0 = load_gthr(v, b);
+  if (enc_key(g0) < pub) pub = enc_key(g0);
+  double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
   Acc Dp = std::is_same_v<E, float> ? (Acc)(thr - (double)EP) : (Acc)((int32_t)thr - (int32_t)EP);
   const uint32_t steps = 1u << I.no;
   // T' rows through a buffer resource: per-lane byte offset in a VGPR (fixed),
@@ -242,6 +246,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
     ev = load(t + 10);
     if (((q + 1) & 7) == 0) {
       const double g = load_gthr(v, b);
+      if (enc_key(g) < pub) pub = enc_key(g);
       if (g < thr) retune(g);
     }
   }
