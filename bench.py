@@ -166,23 +166,24 @@ def extra_batched(dev, plain_loop=True, tune=True):
         _time(eager.run, 3)
         _lib.prof_enable(False)
         wms, wn = _lib.prof_collect("walk_topk")
-    # plain: one full solve (its own launch sequence) per instance
-    L = _lib.lib()
-    Qs = [torch.from_numpy(np.ascontiguousarray(Q[b, :int(n), :int(n)])).to(dev) for b, n in enumerate(ns)]
-    ws_bytes = max(L.qubo_bf_workspace_size(int(n), 1, _lib.QUBO_F32) for n in ns)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    en = torch.empty((len(ns), 1), dtype=torch.float64, device=dev)
-    mk = torch.empty((len(ns), 1), dtype=torch.int64, device=dev)
-    st = torch.empty(len(ns), dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream(dev).cuda_stream
-
-    def plain():
-        for b, n in enumerate(ns):
-            _lib.check(L.qubo_bf_solve(Qs[b].data_ptr(), int(n), int(n), _lib.QUBO_F32, 1, en[b].data_ptr(),
-                                       mk[b].data_ptr(), st[b:b + 1].data_ptr(), ws.data_ptr(), ws_bytes, stream))
-
     t_plain, same = float("nan"), None
     if plain_loop:
+        # plain: one full solve (its own launch sequence) per instance
+        L = _lib.lib()
+        Qs = [torch.from_numpy(np.ascontiguousarray(Q[b, :int(n), :int(n)])).to(dev) for b, n in enumerate(ns)]
+        ws_bytes = max(L.qubo_bf_workspace_size(int(n), 1, _lib.QUBO_F32) for n in ns)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        en = torch.empty((len(ns), 1), dtype=torch.float64, device=dev)
+        mk = torch.empty((len(ns), 1), dtype=torch.int64, device=dev)
+        st = torch.empty(len(ns), dtype=torch.int32, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+
+        def plain():
+            for b, n in enumerate(ns):
+                _lib.check(L.qubo_bf_solve(Qs[b].data_ptr(), int(n), int(n), _lib.QUBO_F32, 1, en[b].data_ptr(),
+                                           mk[b].data_ptr(), st[b:b + 1].data_ptr(), ws.data_ptr(), ws_bytes,
+                                           stream))
+
         plain()
         t_plain = _time(plain, 2)
         same = bool(torch.equal(en, e_b))

@@ -144,6 +144,7 @@ const char* qubo_version(void);
  * workspace size, so query it again after a change.
  *   QUBO_TUNE_SINGLE_OUTER_BITS   max outer (Gray-walked) bits per work unit, single solve
  *   QUBO_TUNE_SINGLE_UNIT_BITS    prefix bits reserved for work units, single solve
+ *                                 (upper bound; mid-size n reserves max(8, n - 18))
  *   QUBO_TUNE_BATCHED_OUTER_BITS  max outer bits per work unit, batched / logZ
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
  *   QUBO_TUNE_KPRIME              candidate list length override (float path;

@@ -237,11 +237,15 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   return v;
 }
 
-PlanParams single_params(int kp) {
+PlanParams single_params(int kp, int n) {
   const Tuning& t = tuning();
   PlanParams pp;
   pp.no_max = clampi(t.single_outer, 0, kMaxOuter);
-  pp.ub_min = clampi(t.single_unit, 0, 62);
+  // unit bits reserved before outer bits are granted: the knob, lowered for
+  // mid-size n so that units keep a useful number of Gray steps (measured:
+  // n=24 -> 8, n=28 -> 10, n >= 30 -> 12)
+  const int want = n - 18 > 8 ? n - 18 : 8;
+  pp.ub_min = clampi(t.single_unit < want ? t.single_unit : want, 0, 62);
   pp.inner = kInner;
   pp.kprime = kp;
   pp.waves = kMaxGridWaves;  // replaced by the real grid at launch
@@ -389,7 +393,7 @@ size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt) {
   if (n < 1 || n > 63 || !valid_dtype(dt)) return 0;
   const bool is_int = dt == QUBO_I32;
   if (check_k(k, is_int) != QUBO_OK) return 0;
-  return make_layout(1, n, single_params(kprime_for(k, is_int)), 0, 0).total;
+  return make_layout(1, n, single_params(kprime_for(k, is_int), n), 0, 0).total;
 }
 
 int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
@@ -401,7 +405,7 @@ int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void*
   const bool is_int = dt == QUBO_I32;
   if (int rc = check_k(k, is_int)) return rc;
   const int kp = kprime_for(k, is_int);
-  const PlanParams pp = single_params(kp);
+  const PlanParams pp = single_params(kp, n);
   const Layout L = make_layout(1, n, pp, 0, 0);
   if (ws_bytes < L.total)
     return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);

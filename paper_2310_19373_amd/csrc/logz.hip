@@ -271,29 +271,26 @@ __global__ void finalize_logz_kernel(Views v, const float* beta, double* logz, i
 
 // Factor tables of the forward and adjoint walks: per step, b(t, j) =
 // 2^(-bb (T'(g(t); j) - min_j T')) in the layout of T', and
-// tref(t) = min_j T'(g(t); j) + E_O(g(t)).  One wave per step, lane = entry.
+// tref(t) = min_j T'(g(t); j) + E_O(g(t)).  blockIdx.x: instance; blockIdx.y:
+// chunk of 64 of its steps; one wave per step, lane = table entry.
 __global__ void __launch_bounds__(256) prep_exp_tables_kernel(Views v, const float* beta, int inner) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t total = v.hdr->total_steps;
+  const int b = blockIdx.x;
+  const Inst* I = &v.inst[b];
+  if (I->status != 0) return;
+  const int64_t steps = int64_t(1) << I->no;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int width = 1 << inner;
-  const float* tab = (const float*)v.tab;
-  float* etab = (float*)v.etab;
-  for (int64_t s = wave; s < total; s += nwaves) {
-    int lo = 0, hi = v.batch;  // instance of step s
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (v.inst[mid].tab_off <= s) lo = mid;
-      else hi = mid;
-    }
-    const float bbf = (float)(fabs((double)beta[lo]) * kLog2e);
-    const float tv = lane < width ? tab[s * width + lane] : __builtin_inff();
+  const float bbf = (float)(fabs((double)beta[b]) * kLog2e);
+  const float* tab = (const float*)v.tab + I->tab_off * width;
+  float* etab = (float*)v.etab + I->tab_off * width;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  for (int64_t t = c0 + w; t < steps && t < c0 + 64; t += 4) {
+    const float tv = lane < width ? tab[t * width + lane] : __builtin_inff();
     float m = tv;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
-    if (lane < width) etab[s * width + lane] = exp2_fast(-bbf * (tv - m));
-    if (lane == 0) v.tref[s] = (double)m + v.eod[s];
+    if (lane < width) etab[t * width + lane] = exp2_fast(-bbf * (tv - m));
+    if (lane == 0) v.tref[I->tab_off + t] = (double)m + v.eod[I->tab_off + t];
   }
 }
 
@@ -736,9 +733,9 @@ __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta,
 
 hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,
                                  hipStream_t s) {
-  int64_t waves = steps_bound < 1 ? 1 : steps_bound;
-  if (waves > 4096) waves = 4096;
-  hipLaunchKernelGGL(prep_exp_tables_kernel, dim3((int)((waves + 3) / 4)), dim3(256), 0, s, v, beta, inner);
+  const int64_t per_inst = (steps_bound + v.batch - 1) / v.batch;  // steps of one instance, bound
+  const dim3 grid((unsigned)v.batch, (unsigned)((per_inst + 63) / 64 > 0 ? (per_inst + 63) / 64 : 1));
+  hipLaunchKernelGGL(prep_exp_tables_kernel, grid, dim3(256), 0, s, v, beta, inner);
   return hipGetLastError();
 }
 

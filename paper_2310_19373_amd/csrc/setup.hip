@@ -345,74 +345,69 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   }
 }
 
-__device__ int find_by_tab(const Views& v, int64_t s) {
-  int lo = 0, hi = v.batch;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (v.inst[mid].tab_off <= s) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
 template <class W, class E>
 __global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
-  // A wave takes 64 consecutive steps: lane i computes the scalars of step
-  // s0 + i (its own instance, its own O(no^2) sum), parks H in LDS, and the
-  // wave then writes the 64 table rows one coalesced row at a time.
+  // blockIdx.x: instance; blockIdx.y: chunk of 256 of its steps.  The entries
+  // the step scalars need -- S(u, B+l) for inner u and S(B+l, B+l2) for outer
+  // l, l2 -- are staged in LDS.  A wave takes 64 consecutive steps: lane i
+  // computes the scalars of step s0 + i, parks H in LDS, and the wave then
+  // writes the 64 table rows one coalesced row at a time.
   __shared__ W hs[4][6][kWave];
+  __shared__ W qo[(6 + kMaxOuter) * kMaxOuter];
+  const int b = blockIdx.x;
+  const Inst* I = &v.inst[b];
+  if (I->status != 0) return;  // the walks skip such instances
+  const int B = I->B, no = I->no, nm = v.nmax;
+  const int64_t steps = int64_t(1) << no;
+  const int64_t c0 = (int64_t)blockIdx.y * 256;
+  if (c0 >= steps) return;
+  const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
+  // row r < 6: inner row u = r; row 6 + l: outer row B + l; column l2: B + l2
+  for (int e = threadIdx.x; e < (6 + no) * no; e += blockDim.x) {
+    const int r = e / no, l2 = e % no;
+    qo[e] = (r < 6 && r >= B) ? (W)0 : qs[(int64_t)(r < 6 ? r : B + r - 6) * nm + B + l2];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t total = v.hdr->total_steps;
+  const int64_t s0 = c0 + (int64_t)w * kWave;  // the wave's first step
+  if (s0 >= steps) return;
   const int width = 1 << inner, per = width / 16;
-  E* tab = (E*)v.tab;
-  for (int64_t s0 = wave * kWave; s0 < total; s0 += nwaves * kWave) {
-    const int64_t s = s0 + lane;
-    W H[6] = {0, 0, 0, 0, 0, 0};
-    W eo = 0;
-    if (s < total) {
-      const int b = v.batch == 1 ? 0 : find_by_tab(v, s);
-      const Inst* I = &v.inst[b];
-      const int64_t t = s - I->tab_off;
-      const int B = I->B, no = I->no;
-      if (I->status == 0 && t < (int64_t(1) << no)) {
-        const W* qs = (const W*)v.qs + (int64_t)b * v.nmax * v.nmax;
-        const uint64_t o = gray((uint64_t)t);
-        for (int l = 0; l < no; ++l) {
-          if (!((o >> l) & 1)) continue;
-          const int a = B + l;
-          W row = qs[(int64_t)a * v.nmax + a];
-          for (int l2 = l + 1; l2 < no; ++l2)
-            if ((o >> l2) & 1) row += qs[(int64_t)a * v.nmax + B + l2];
-          eo += row;
+  const int64_t t = s0 + lane;
+  W H[6] = {0, 0, 0, 0, 0, 0};
+  W eo = 0;
+  if (t < steps) {
+    const uint64_t o = gray((uint64_t)t);
+    for (int l = 0; l < no; ++l) {
+      if (!((o >> l) & 1)) continue;
+      W row = qo[(6 + l) * no + l];
+      for (int l2 = l + 1; l2 < no; ++l2)
+        if ((o >> l2) & 1) row += qo[(6 + l) * no + l2];
+      eo += row;
 #pragma unroll
-          for (int u = 0; u < 6; ++u)
-            if (u < B) H[u] += qs[(int64_t)u * v.nmax + a];
-        }
-      }
-      v.eod[s] = (double)eo;
-      v.eoi[s] = (int32_t)(-eo);
-      StepRec* r = &v.rec[s];
-      r->eo = (double)eo;
-#pragma unroll
-      for (int u = 0; u < 6; ++u) r->h[u] = (double)H[u];
-      r->neo = (int32_t)(-eo);
-      r->pad = 0;
+      for (int u = 0; u < 6; ++u) H[u] += qo[u * no + l];  // zero rows for u >= B
     }
+    const int64_t s = I->tab_off + t;
+    v.eod[s] = (double)eo;
+    v.eoi[s] = (int32_t)(-eo);
+    StepRec* r = &v.rec[s];
+    r->eo = (double)eo;
 #pragma unroll
-    for (int u = 0; u < 6; ++u) hs[w][u][lane] = H[u];
-    __builtin_amdgcn_wave_barrier();
-    const int nst = (int)min<int64_t>(kWave, total - s0);
-    for (int k = 0; k < nst; ++k) {
-      // H_u is zero for u >= B, so summing every set lane bit is the same sum
-      W tj = 0;
+    for (int u = 0; u < 6; ++u) r->h[u] = (double)H[u];
+    r->neo = (int32_t)(-eo);
+    r->pad = 0;
+  }
 #pragma unroll
-      for (int u = 0; u < 6; ++u)
-        if ((lane >> u) & 1) tj += hs[w][u][k];
-      if (lane < width) tab[(s0 + k) * width + (lane & 15) * per + (lane >> 4)] = (E)tj;
-    }
-    __builtin_amdgcn_wave_barrier();
+  for (int u = 0; u < 6; ++u) hs[w][u][lane] = H[u];
+  __builtin_amdgcn_wave_barrier();
+  E* tab = (E*)v.tab + I->tab_off * width;
+  const int nst = (int)(steps - s0 < kWave ? steps - s0 : kWave);
+  for (int k = 0; k < nst; ++k) {
+    // H_u is zero for u >= B, so summing every set lane bit is the same sum
+    W tj = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+      if ((lane >> u) & 1) tj += hs[w][u][k];
+    if (lane < width) tab[(s0 + k) * width + (lane & 15) * per + (lane >> 4)] = (E)tj;
   }
 }
 
@@ -461,14 +456,14 @@ hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s) {
 }
 
 hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int64_t steps_bound, hipStream_t s) {
-  // one wave per 64 steps, at most 8 waves per compute unit
-  int64_t waves = (steps_bound + kWave - 1) / kWave;
-  if (waves > 2048) waves = 2048;
-  const int blocks = waves > 4 ? (int)((waves + 3) / 4) : 1;
+  // one block per (instance, chunk of 256 steps); steps_bound / batch bounds
+  // the steps of one instance
+  const int64_t per_inst = (steps_bound + v.batch - 1) / v.batch;
+  const dim3 grid((unsigned)v.batch, (unsigned)((per_inst + 255) / 256 > 0 ? (per_inst + 255) / 256 : 1));
   if (is_int)
-    hipLaunchKernelGGL((prep_tables_kernel<int64_t, int32_t>), dim3(blocks), dim3(256), 0, s, v, inner);
+    hipLaunchKernelGGL((prep_tables_kernel<int64_t, int32_t>), grid, dim3(256), 0, s, v, inner);
   else
-    hipLaunchKernelGGL((prep_tables_kernel<double, float>), dim3(blocks), dim3(256), 0, s, v, inner);
+    hipLaunchKernelGGL((prep_tables_kernel<double, float>), grid, dim3(256), 0, s, v, inner);
   return hipGetLastError();
 }
 
