@@ -153,7 +153,7 @@ SplitH split_host(int n, const PlanParams& pp) {
 }
 
 struct Layout {
-  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, eod, eoi, slots, part, lt, umap, etab, tref, total;
+  size_t hdr, inst, gthr, flush, qs, ei, tab, rec, eod, eoi, slots, part, lt, umap, etab, tref, dlist, total;
   int64_t umap_cap;
 };
 
@@ -198,12 +198,14 @@ Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_u
   L.umap = o;
   L.umap_cap = (batch > 1 && (int64_t)batch * units <= kUnitMapMax) ? (int64_t)batch * units : 0;
   o += al(4 * (size_t)L.umap_cap);
-  L.etab = L.tref = 0;
+  L.etab = L.tref = L.dlist = 0;
   if (exp_tables) {
     L.etab = o;
     o += al(4 * (size_t)batch * steps * width);
     L.tref = o;
     o += al(8 * (size_t)batch * steps);
+    L.dlist = o;
+    o += al(8 * (size_t)batch * units);
   }
   L.total = o;
   return L;
@@ -229,6 +231,7 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.umap_cap = L.umap_cap;
   v.etab = L.etab ? (void*)(p + L.etab) : nullptr;
   v.tref = L.tref ? (double*)(p + L.tref) : nullptr;
+  v.dlist = L.dlist ? (uint64_t*)(p + L.dlist) : nullptr;
   v.factor = L.etab && tuning().logz_factored > 0;
   v.seed_sweeps = tuning().seed_sweeps;
   v.batch = batch;

@@ -87,6 +87,7 @@ struct Header {
   int32_t nmax;
   int32_t waves;          // waves of the persistent walk grid
   int32_t chunk;          // largest run of work units per queue pull
+  uint64_t direct_count;  // log-partition: units deferred to the direct-form pass
   QueueSeg seg[kXcds];    // persistent work queue
 };
 

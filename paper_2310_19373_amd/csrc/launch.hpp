@@ -27,6 +27,7 @@ struct Views {
   void* etab;      // log-partition: factor table b(t, j), layout of tab (float), or null
   double* tref;    // log-partition: min_j T'(g(t); j) + E_O(g(t)) per step, or null
   int factor;      // log-partition: 1 = factored form allowed
+  uint64_t* dlist; // log-partition: units deferred to the direct-form pass, or null
   int seed_sweeps; // descent passes of the threshold seed (0: no seeding)
   int64_t umap_cap;
   int batch, nmax;
@@ -47,8 +48,6 @@ struct PlanParams {
 // instance of size n_single.  beta (may be null): instance sign = sign(beta).
 hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta,
                        const PlanParams& pp, hipStream_t s);
-// rewind the persistent work queue (between two walks over one plan)
-hipError_t launch_reset_queue(const Views& v, hipStream_t s);
 // prep: symmetric Q, sums, E_I table, float/int validation.
 hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
                             int inner, hipStream_t s);

@@ -104,6 +104,31 @@ __device__ __forceinline__ void block_dot(float (&acc)[4], float t, const float*
         "v"(A[16 * K + 13]), "v"(A[16 * K + 14]), "v"(A[16 * K + 15]));
 }
 
+// As block_dot for K = 0, but the first four states start the accumulators
+// (v_mul_f32 instead of zeroing them and accumulating).
+__device__ __forceinline__ void block_dot_first(float (&acc)[4], float t, const float* A) {
+  asm("s_nop 1\n"
+      "v_mul_f32_dpp %0, %4, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %1, %4, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %2, %4, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+      "v_mul_f32_dpp %3, %4, %8 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %0, %4, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %10 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %11 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %12 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %0, %4, %13 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %15 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %0, %4, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %1, %4, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %2, %4, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f32_dpp %3, %4, %20 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+      : "=&v"(acc[0]), "=&v"(acc[1]), "=&v"(acc[2]), "=&v"(acc[3])
+      : "v"(t), "v"(A[0]), "v"(A[1]), "v"(A[2]), "v"(A[3]), "v"(A[4]), "v"(A[5]), "v"(A[6]), "v"(A[7]), "v"(A[8]),
+        "v"(A[9]), "v"(A[10]), "v"(A[11]), "v"(A[12]), "v"(A[13]), "v"(A[14]), "v"(A[15]));
+}
+
 // Per-lane range of the finite entries of C' and the factored-form decision
 // (uniform: every valid lane must satisfy the bound).
 template <int NB>
@@ -142,14 +167,48 @@ __device__ __forceinline__ double wave_lse2(double l) {
   return m + log2(wave_sum(t));
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_exp_kernel(Views v, const float* beta) {
+// Units of the two passes.  Pass 0 (factored) walks the queue's units and
+// sends a unit that fails the factored-form bound -- or every unit when the
+// factored form is switched off -- to a list; pass 1 (direct) strides over
+// that list.  Each pass is its own kernel, so each gets its own register
+// budget; the list is usually empty and pass 1 then ends at once.
+template <int PASS>
+struct PassUnits {
+  WorkIter it;
+  uint64_t i, count, stride;
+  __device__ PassUnits(const Views& v, uint64_t total_units)
+      : it(v, total_units),
+        i((uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)),
+        count(PASS == 1 ? uniform_u64(gp((const Header*)v.hdr)->direct_count) : 0),
+        stride((uint64_t)gridDim.x * kWavesPerBlock) {}
+  __device__ __forceinline__ bool next(const Views& v, int lane, uint64_t& u) {
+    if constexpr (PASS == 0) {
+      return it.next(v, lane, u);
+    } else {
+      if (i >= count) return false;
+      u = uniform_u64(gp(v.dlist)[i]);
+      i += stride;
+      return true;
+    }
+  }
+};
+
+// Appends unit u to the direct pass's list (all lanes call; lane 0 adds).
+__device__ __forceinline__ void defer_unit(const Views& v, uint64_t u, int lane) {
+  const uint64_t idx = uniform_u64(
+      atomicAdd((unsigned long long*)&v.hdr->direct_count, lane == 0 ? 1ull : 0ull));
+  if (lane == 0) gp(v.dlist)[idx] = u;
+}
+
+template <int PASS>
+__device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta) {
   __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   double* myc = ctab[threadIdx.x >> 6];
   const uint64_t total_units = uniform_u64(gp((const Header*)v.hdr)->total_units);
-  WorkIter it(v, total_units);
+  PassUnits<PASS> units(v, total_units);
   uint64_t u;
-  while (it.next(v, lane, u)) {
+  while (units.next(v, lane, u)) {
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     const InstU I = load_inst(v, b);
     if (I.status != 0) {
@@ -164,11 +223,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
     const float bbf = (float)bb;
     const uint32_t steps = 1u << I.no;
     const int qoff = (lane & 15) * 16;
-    float cmin = 0.f;
-    const bool fac = v.factor && factor_ok(C, bbf, valid, cmin);
     double K = EP;  // E_P + X_PO(p, g(t)): the lane's share of the step's constant
     double r = 0.0, S = 0.0;
-    if (fac) {
+    if constexpr (PASS == 0) {
+      float cmin = 0.f;
+      if (!(v.factor && factor_ok(C, bbf, valid, cmin))) {
+        defer_unit(v, u, lane);
+        continue;
+      }
       to_factors(C, bbf, cmin);
       const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(gp((const float*)v.etab) + I.tab_off * kInnerStates), (short)0,
@@ -190,20 +252,22 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         }
         const double lt = cm + trc + K;  // lower bound of the block's values
         double ct = -bb * (lt - r);
-        if (ct > kRebase) {
-          S *= (double)exp2_fast((float)-ct);
-          r = lt;
-          ct = 0.0;
+        if (__builtin_expect(ballot(ct > kRebase) != 0, 0)) {  // rare: move the lane's reference
+          if (ct > kRebase) {
+            S *= (double)exp2_fast((float)-ct);
+            r = lt;
+            ct = 0.0;
+          }
         }
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        block_dot<0>(acc, bc.x, C);
+        float acc[4];
+        block_dot_first(acc, bc.x, C);
         block_dot<1>(acc, bc.y, C);
         block_dot<2>(acc, bc.z, C);
         block_dot<3>(acc, bc.w, C);
         S = __builtin_fma((double)((acc[0] + acc[1]) + (acc[2] + acc[3])), (double)exp2_fast((float)ct), S);
       }
     } else {
-      // beta = 0: a tiny negative slope keeps the sentinel entries (+inf) at
+      // direct form.  beta = 0: a tiny negative slope keeps the sentinel entries (+inf) at
       // weight 0 without changing any valid weight.
       const float nb = bb > 0.0 ? -bbf : -1e-30f;
       const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
@@ -248,6 +312,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
     const double lu = wave_lse2(l);
     if (lane == 0) gp(v.part)[u] = lu;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_exp_fac_kernel(Views v,
+                                                                                            const float* beta) {
+  walk_exp_body<0>(v, beta);
+}
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_exp_direct_kernel(Views v,
+                                                                                               const float* beta) {
+  walk_exp_body<1>(v, beta);
 }
 
 // One thread per instance: log-sum-exp of its units' log2 sums (in unit order).
@@ -402,15 +475,15 @@ __device__ __forceinline__ void block_moments(const float (&w)[kGradStates], flo
 
 __device__ __forceinline__ int pidx(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_grad_kernel(Views v, const float* beta, const double* logz,
-                                                          int npairs) {
+template <int PASS>
+__device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta, const double* logz, int npairs) {
   __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   double* myc = ctab[threadIdx.x >> 6];
   const uint64_t total_units = uniform_u64(gp((const Header*)v.hdr)->total_units);
-  WorkIter it(v, total_units);
+  PassUnits<PASS> units(v, total_units);
   uint64_t u;
-  while (it.next(v, lane, u)) {
+  while (units.next(v, lane, u)) {
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
     const InstU I = load_inst(v, b);
     const gptr<double> out = gp(v.part) + (int64_t)u * npairs;
@@ -426,8 +499,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     const uint32_t steps = 1u << I.no;
     const int qoff = (lane & 15) * 8;
     float cmin = 0.f;
-    const bool fac = v.factor && factor_ok(C, bbf, valid, cmin);
-    if (fac) to_factors(C, bbf, cmin);
+    constexpr bool fac = PASS == 0;  // pass 0: factored form; pass 1: direct form
+    if constexpr (PASS == 0) {
+      if (!(v.factor && factor_ok(C, bbf, valid, cmin))) {
+        defer_unit(v, u, lane);
+        continue;
+      }
+      to_factors(C, bbf, cmin);
+    }
     // factored: b(t, j) rows and tref; direct: T' rows and E_O
     const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(gp((const float*)(fac ? v.etab : v.tab)) + I.tab_off * kGradStates), (short)0,
@@ -452,7 +531,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     // Block sums of one step: y[0] = s = sum_j w(t, j), y[1 + a] = v_a =
     // sum_j w(t, j) j_a; W[j] += w(t, j).  The caller has moved K to step t.
     const double cm = (double)cmin;
-    const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_kernel
+    const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_body
     auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1]) {
       float w[kGradStates];
       float va[kGradInner];
@@ -628,8 +707,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         }
       }
     };
-    if (fac) walk(std::true_type{});
-    else walk(std::false_type{});
+    walk(std::integral_constant<bool, fac>{});
 
     // ---- assemble the unit's moments sum_x w x_i x_j (i <= j)
     const int n = I.n, B = I.B, no = I.no, pos0 = B + no;
@@ -691,6 +769,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   }
 }
 
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_grad_fac_kernel(
+    Views v, const float* beta, const double* logz, int npairs) {
+  walk_grad_body<0>(v, beta, logz, npairs);
+}
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_grad_direct_kernel(
+    Views v, const float* beta, const double* logz, int npairs) {
+  walk_grad_body<1>(v, beta, logz, npairs);
+}
+
 // One block per instance: sum the units' moments in order, scale, write.
 __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta, const float* grad_logz,
                                      float* grad_q, float* grad_beta, int32_t* status, int npairs) {
@@ -741,7 +828,8 @@ hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, 
 
 hipError_t launch_walk_exp(const Views& v, const float* beta, int waves, hipStream_t s) {
   const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  hipLaunchKernelGGL(walk_exp_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta);
+  hipLaunchKernelGGL(walk_exp_fac_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta);
+  hipLaunchKernelGGL(walk_exp_direct_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta);
   return hipGetLastError();
 }
 
@@ -754,7 +842,8 @@ hipError_t launch_walk_grad(const Views& v, const float* beta, const double* log
                             int n_moments, hipStream_t s) {
   const int64_t nb = (total_waves + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = nb < 1 ? 1 : (int)nb;
-  hipLaunchKernelGGL(walk_grad_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta, logz, n_moments);
+  hipLaunchKernelGGL(walk_grad_fac_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta, logz, n_moments);
+  hipLaunchKernelGGL(walk_grad_direct_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta, logz, n_moments);
   return hipGetLastError();
 }
 

@@ -111,6 +111,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
       v.hdr->seg[x].end = tu * (uint64_t)(x + 1) / kXcds;
     }
     v.hdr->total_units = tu;
+    v.hdr->direct_count = 0;
     v.hdr->total_steps = ss[nt - 1];
     v.hdr->total_slots = sl[nt - 1];
     v.hdr->batch = batch;
@@ -121,13 +122,6 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
     if (c > pp.chunk_cap) c = pp.chunk_cap;
     v.hdr->chunk = c < 1 ? 1 : (int32_t)c;
   }
-}
-
-// Rewinds the persistent work queue so a second walk can run over the same
-// plan (written by a kernel, not a memset, to stay graph-capture friendly).
-__global__ void reset_queue_kernel(Views v) {
-  const uint64_t tu = v.hdr->total_units;
-  for (int x = 0; x < kXcds; ++x) v.hdr->seg[x].next = tu * (uint64_t)x / kXcds;
 }
 
 template <class T>
@@ -416,11 +410,6 @@ __global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
 hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta, const PlanParams& pp,
                        hipStream_t s) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, v, ns, n_single, beta, pp);
-  return hipGetLastError();
-}
-
-hipError_t launch_reset_queue(const Views& v, hipStream_t s) {
-  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, v);
   return hipGetLastError();
 }
 
