@@ -103,6 +103,37 @@ int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns,
                           void* energies, uint64_t* masks, int32_t* status, void* ws, size_t ws_bytes,
                           void* hip_stream);
 
+/* --------------------------------------------------- prefix-range solves */
+
+/* Workspace bytes for qubo_bf_solve_range with these n, k, dt and p_bits (any
+ * range); 0 for invalid arguments. */
+size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits);
+
+/*
+ * Part of one solve, for long enumerations cut into resumable pieces: the k
+ * lowest states among the masks whose top p_bits bits (p = mask >> (n - p_bits))
+ * lie in [p_begin, p_end) -- the fixed-prefix sub-walks of Sec. 3.1, each a
+ * contiguous block of masks.  Arguments, outputs and status as qubo_bf_solve;
+ * the result is exact (and, for float32 Q, certified) for that range, so the
+ * k lowest of the union of the results of disjoint ranges (qubo_bf_merge_topk)
+ * is the result of qubo_bf_solve.
+ *   p_bits   1 .. min(20, n - 12)
+ *   p_begin, p_end   0 <= p_begin < p_end <= 2^p_bits
+ */
+int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int p_bits, int64_t p_begin,
+                        int64_t p_end, void* energies, uint64_t* masks, int32_t* status, void* ws,
+                        size_t ws_bytes, void* hip_stream);
+
+/*
+ * The k lowest (energy, mask) pairs of `count` result lists of k_in entries
+ * each (device, [count][k_in], energies double for QUBO_F32 / int64_t for
+ * QUBO_I32, masks uint64), as written by qubo_bf_solve_range for disjoint
+ * ranges of one instance; sentinel entries are skipped and missing outputs
+ * hold the sentinels.  k: 1 .. 64.  One launch on hip_stream, no workspace.
+ */
+int qubo_bf_merge_topk(int count, int k_in, const void* energies_in, const uint64_t* masks_in, qubo_dtype dt,
+                       int k, void* energies, uint64_t* masks, void* hip_stream);
+
 /* ------------------------------------------------------- log-partition */
 
 /* Workspace bytes for qubo_logz_fwd / qubo_logz_bwd (the larger of the two). */
@@ -131,6 +162,19 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
 int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, const double* logz,
                   const float* grad_logz, float* grad_Q, float* grad_beta, int32_t* status, void* ws,
                   size_t ws_bytes, void* hip_stream);
+
+/*
+ * Second moments of p(x) = exp(-beta f(x) - logZ), by the same re-enumeration
+ * as qubo_logz_bwd (an extension with a plain definition):
+ *   moments[b][i][j] = E_p[x_i x_j]  for i <= j < n_b (E_p[x_i] on the
+ *                      diagonal: the marginals), 0 elsewhere; float64
+ *   mean_energy[b]   = E_p[f]  (device, [batch] double; may be NULL)
+ *   logz   device, [batch] double, the forward result for the same inputs
+ * Other arguments and the workspace as qubo_logz_bwd.
+ */
+int qubo_logz_moments(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta,
+                      const double* logz, double* moments, double* mean_energy, int32_t* status, void* ws,
+                      size_t ws_bytes, void* hip_stream);
 
 /* ------------------------------------------------------------ utilities */
 

@@ -41,10 +41,14 @@ SIGNATURES = {
     "qubo_bf_workspace_size": (_sz, [_i, _i, _i]),
     "qubo_bf_solve": (_i, [_vp, _i, _i64, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_bf_batched_workspace_size": (_sz, [_i, _i, _i, _i]),
+    "qubo_bf_range_workspace_size": (_sz, [_i, _i, _i, _i]),
+    "qubo_bf_solve_range": (_i, [_vp, _i, _i64, _i, _i, _i, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qubo_bf_merge_topk": (_i, [_i, _i, _vp, _vp, _i, _i, _vp, _vp, _vp]),
     "qubo_bf_solve_batched": (_i, [_i, _vp, _i, _vp, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_logz_workspace_size": (_sz, [_i, _i]),
     "qubo_logz_fwd": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_logz_bwd": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qubo_logz_moments": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_last_error": (ctypes.c_char_p, []),
     "qubo_version": (ctypes.c_char_p, []),
     "qubo_bf_set_tuning": (_i, [_i, _i]),

@@ -114,6 +114,52 @@ def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = Tr
     return en, masks
 
 
+def solve_range(Q, k: int, p_bits: int, p_begin: int, p_end: int, *, check_lower: bool = True):
+    """The k lowest states among the masks whose top p_bits bits lie in
+    [p_begin, p_end) -- one resumable piece of solve(Q, k).  Results of
+    disjoint ranges combine with merge_topk into the result of solve.
+    Returns (energies, masks) like solve; raises UncertainError if the float
+    certificate fails for the range."""
+    Qd = _as_device(Q)
+    if Qd.ndim != 2 or Qd.shape[0] != Qd.shape[1]:
+        raise ValueError("Q must be square")
+    if check_lower:
+        _check_upper(Qd)
+    n = Qd.shape[0]
+    dt = _qdtype(Qd)
+    L = _lib.lib()
+    ws_bytes = L.qubo_bf_range_workspace_size(n, k, dt, p_bits)
+    if ws_bytes == 0:
+        raise ValueError(f"invalid arguments n={n}, k={k}, p_bits={p_bits}: {_lib.last_error()}")
+    dev = Qd.device
+    with torch.cuda.device(dev):
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=dev)
+        masks = torch.empty(k, dtype=torch.int64, device=dev)
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+        _lib.check(L.qubo_bf_solve_range(Qd.data_ptr(), n, n, dt, k, p_bits, p_begin, p_end, en.data_ptr(),
+                                         masks.data_ptr(), status.data_ptr(), ws.data_ptr(), ws_bytes, _stream(dev)))
+        _raise_status(status)
+    return en, masks
+
+
+def merge_topk(results, k: int):
+    """The k lowest (energy, mask) pairs over a list of (energies, masks)
+    results of solve_range on disjoint ranges of one instance (device merge)."""
+    if not results:
+        raise ValueError("nothing to merge")
+    en = torch.stack([r[0] for r in results]).contiguous()
+    mk = torch.stack([r[1] for r in results]).contiguous()
+    dev = en.device
+    dt = _lib.QUBO_F32 if en.dtype == torch.float64 else _lib.QUBO_I32
+    out_e = torch.empty(k, dtype=en.dtype, device=dev)
+    out_m = torch.empty(k, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _lib.check(_lib.lib().qubo_bf_merge_topk(en.shape[0], en.shape[1], en.data_ptr(), mk.data_ptr(), dt, k,
+                                                 out_e.data_ptr(), out_m.data_ptr(), _stream(dev)))
+    return out_e, out_m
+
+
 class BatchedSolver:
     """Persistent buffers for repeated batched solves of one shape.
 
@@ -285,3 +331,48 @@ def logz(Q, beta, ns=None):
     ns = _as_device(ns, torch.int32, dev)
     out = LogZ.apply(Q, beta, ns)
     return out[0] if single else out
+
+
+def logz_moments(Q, beta, ns=None):
+    """logZ with the second moments of p(x) = exp(-beta f(x) - logZ).
+
+    Returns (logz [batch] float64, moments [batch, nmax, nmax] float64 with
+    E_p[x_i x_j] for i <= j < n (marginals E_p[x_i] on the diagonal, zeros
+    elsewhere), mean_energy [batch] float64 = E_p[f]); a single (n, n) Q gives
+    unbatched results.
+    """
+    single = False
+    if not isinstance(Q, torch.Tensor):
+        Q = torch.as_tensor(np.asarray(Q))
+    if Q.ndim == 2:
+        Q = Q.unsqueeze(0)
+        single = True
+    if Q.dtype != torch.float32:
+        raise TypeError("Q must be float32")
+    Q = _as_device(Q, torch.float32)
+    _check_upper(Q)
+    dev = Q.device
+    batch, nmax = Q.shape[0], Q.shape[1]
+    if not isinstance(beta, torch.Tensor):
+        beta = torch.full((batch,), float(beta), dtype=torch.float32, device=dev)
+    beta = beta.to(device=dev, dtype=torch.float32).reshape(-1).expand(batch).contiguous()
+    nsd = torch.full((batch,), nmax, dtype=torch.int32, device=dev) if ns is None else _as_device(ns, torch.int32, dev)
+    lz = LogZ.apply(Q, beta, nsd).detach()
+    mom = torch.empty((batch, nmax, nmax), dtype=torch.float64, device=dev)
+    mean = torch.empty(batch, dtype=torch.float64, device=dev)
+    status = torch.empty(batch, dtype=torch.int32, device=dev)
+    ws, nbytes = _logz_ws(batch, nmax, dev)
+    with torch.cuda.device(dev):
+        _lib.check(_lib.lib().qubo_logz_moments(batch, Q.data_ptr(), nmax, nsd.data_ptr(), beta.data_ptr(),
+                                                lz.data_ptr(), mom.data_ptr(), mean.data_ptr(), status.data_ptr(),
+                                                ws.data_ptr(), nbytes, _stream(dev)))
+    _raise_status(status)
+    if single:
+        return lz[0], mom[0], mean[0]
+    return lz, mom, mean
+
+
+def marginals(Q, beta, ns=None):
+    """E_p[x_i] under p(x) = exp(-beta f(x) - logZ): the diagonal of logz_moments."""
+    _, mom, _ = logz_moments(Q, beta, ns)
+    return torch.diagonal(mom, dim1=-2, dim2=-1)

@@ -147,7 +147,7 @@ SplitH split_host(int n, const PlanParams& pp) {
   s.B = n < pp.inner ? n : pp.inner;
   s.L = (n - s.B) < pp.lane_bits ? (n - s.B) : pp.lane_bits;
   const int rest = n - s.B - s.L;
-  s.no = clampi(rest - pp.ub_min, 0, pp.no_max);
+  s.no = clampi(rest - (pp.ub_min > pp.range_bits ? pp.ub_min : pp.range_bits), 0, pp.no_max);
   s.tb = rest - s.no;
   return s;
 }
@@ -242,7 +242,7 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
 
 PlanParams single_params(int kp, int n) {
   const Tuning& t = tuning();
-  PlanParams pp;
+  PlanParams pp{};
   pp.no_max = clampi(t.single_outer, 0, kMaxOuter);
   // unit bits reserved before outer bits are granted: the knob, lowered for
   // mid-size n so that units keep a useful number of Gray steps (measured:
@@ -259,7 +259,7 @@ PlanParams single_params(int kp, int n) {
 
 PlanParams batched_params(int kp) {
   const Tuning& t = tuning();
-  PlanParams pp;
+  PlanParams pp{};
   pp.no_max = clampi(t.batched_outer, 0, kMaxOuter);
   pp.ub_min = 0;
   pp.inner = kInner;
@@ -271,7 +271,7 @@ PlanParams batched_params(int kp) {
 }
 
 PlanParams grad_params() {
-  PlanParams pp;
+  PlanParams pp{};
   pp.no_max = 8;
   pp.ub_min = 0;
   pp.inner = 5;
@@ -306,8 +306,10 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
   HIPCHK(launch_prep_inst(v, Q, ldq, stride, is_int, kInner, s));
   HIPCHK(launch_prep_lanes(v, is_int, s));
-  // single small instances: the walk is shorter than the seed's latency
-  if (ns != nullptr || n_single > 22) HIPCHK(launch_seed(v, is_int, s));
+  // single small instances: the walk is shorter than the seed's latency.  A
+  // prefix-range solve takes no seed: its backing states could lie outside
+  // the range.
+  if (pp.range_bits == 0 && (ns != nullptr || n_single > 22)) HIPCHK(launch_seed(v, is_int, s));
   HIPCHK(launch_prep_tables(v, is_int, kInner, steps_hint, s));
   {
     ProfScope ps("walk_topk", s);
@@ -418,6 +420,63 @@ int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void*
                   masks, status, 16, (hipStream_t)hip_stream);
 }
 
+static int check_range(int n, int p_bits, int64_t p_begin, int64_t p_end) {
+  if (p_bits < 1 || p_bits > 20 || p_bits > n - 12)
+    return fail(QUBO_ERR_INVALID_ARG, "p_bits=%d outside [1, min(20, n - 12)] for n=%d", p_bits, n);
+  if (p_begin < 0 || p_end <= p_begin || p_end > (int64_t(1) << p_bits))
+    return fail(QUBO_ERR_INVALID_ARG, "prefix range [%lld, %lld) outside [0, 2^%d)", (long long)p_begin,
+                (long long)p_end, p_bits);
+  return QUBO_OK;
+}
+
+static PlanParams range_params(int kp, int n, int p_bits, int64_t p_begin, int64_t p_end) {
+  PlanParams pp = single_params(kp, n);
+  pp.range_bits = p_bits;
+  pp.range_begin = p_begin;
+  pp.range_end = p_end;
+  return pp;
+}
+
+size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits) {
+  if (n < 1 || n > 63 || !valid_dtype(dt) || p_bits < 1 || p_bits > 20 || p_bits > n - 12) return 0;
+  const bool is_int = dt == QUBO_I32;
+  if (check_k(k, is_int) != QUBO_OK) return 0;
+  return make_layout(1, n, range_params(kprime_for(k, is_int), n, p_bits, 0, 1), 0, 0).total;
+}
+
+int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int p_bits, int64_t p_begin,
+                        int64_t p_end, void* energies, uint64_t* masks, int32_t* status, void* ws,
+                        size_t ws_bytes, void* hip_stream) {
+  if (!Q || !energies || !masks || !status || !ws) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (n < 1 || n > 63) return fail(QUBO_ERR_INVALID_ARG, "n=%d outside [1, 63]", n);
+  if (ldq < n) return fail(QUBO_ERR_INVALID_ARG, "ldq=%lld < n=%d", (long long)ldq, n);
+  if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+  const bool is_int = dt == QUBO_I32;
+  if (check_k(k, is_int) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
+  if (check_range(n, p_bits, p_begin, p_end) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
+  const int kp = kprime_for(k, is_int);
+  const PlanParams pp = range_params(kp, n, p_bits, p_begin, p_end);
+  const Layout L = make_layout(1, n, pp, 0, 0);
+  if (ws_bytes < L.total) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+  const Views v = make_views(ws, L, 1, n);
+  const SplitH sh = split_host(n, pp);
+  const int64_t units = (p_end - p_begin) << (sh.tb - p_bits);
+  return run_topk(v, Q, ldq, 0, nullptr, n, is_int, k, pp, units, int64_t(1) << sh.no, energies, masks, status,
+                  16, (hipStream_t)hip_stream);
+}
+
+int qubo_bf_merge_topk(int count, int k_in, const void* energies_in, const uint64_t* masks_in, qubo_dtype dt,
+                       int k, void* energies, uint64_t* masks, void* hip_stream) {
+  if (!energies_in || !masks_in || !energies || !masks) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (count < 1 || k_in < 1 || k < 1 || k > kMaxKPrime)
+    return fail(QUBO_ERR_INVALID_ARG, "count=%d, k_in=%d, k=%d: need count, k_in >= 1 and k in [1, %d]", count,
+                k_in, k, kMaxKPrime);
+  if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+  HIPCHK(launch_merge_topk(count, k_in, energies_in, masks_in, dt == QUBO_I32, k, energies, masks,
+                           (hipStream_t)hip_stream));
+  return QUBO_OK;
+}
+
 size_t qubo_bf_batched_workspace_size(int batch, int nmax, int k, qubo_dtype dt) {
   if (batch < 1 || nmax < 1 || nmax > 40 || !valid_dtype(dt)) return 0;
   const bool is_int = dt == QUBO_I32;
@@ -481,11 +540,11 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   return QUBO_OK;
 }
 
-int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, const double* logz,
-                  const float* grad_logz, float* grad_Q, float* grad_beta, int32_t* status, void* ws,
-                  size_t ws_bytes, void* hip_stream) {
-  if (!Q || !ns || !beta || !logz || !grad_logz || !grad_Q || !status || !ws)
-    return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+// Adjoint walk shared by qubo_logz_bwd and qubo_logz_moments.
+static int run_moment_walk(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta,
+                           const double* logz, const float* grad_logz, float* grad_Q, float* grad_beta,
+                           double* moments, double* mean, int32_t* status, void* ws, size_t ws_bytes,
+                           void* hip_stream) {
   if (batch < 1) return fail(QUBO_ERR_INVALID_ARG, "batch=%d < 1", batch);
   if (nmax < 1 || nmax > 32) return fail(QUBO_ERR_INVALID_ARG, "nmax=%d outside [1, 32]", nmax);
   const size_t need = qubo_logz_workspace_size(batch, nmax);
@@ -508,8 +567,26 @@ int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
     ProfScope ps("walk_grad", s);
     HIPCHK(launch_walk_grad(v, beta, logz, waves, np, s));
   }
-  HIPCHK(launch_finalize_grad(v, Q, beta, grad_logz, grad_Q, grad_beta, status, np, s));
+  HIPCHK(launch_finalize_grad(v, Q, beta, grad_logz, grad_Q, grad_beta, moments, mean, status, np, s));
   return QUBO_OK;
+}
+
+int qubo_logz_bwd(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, const double* logz,
+                  const float* grad_logz, float* grad_Q, float* grad_beta, int32_t* status, void* ws,
+                  size_t ws_bytes, void* hip_stream) {
+  if (!Q || !ns || !beta || !logz || !grad_logz || !grad_Q || !status || !ws)
+    return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  return run_moment_walk(batch, Q, nmax, ns, beta, logz, grad_logz, grad_Q, grad_beta, nullptr, nullptr, status,
+                         ws, ws_bytes, hip_stream);
+}
+
+int qubo_logz_moments(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta,
+                      const double* logz, double* moments, double* mean_energy, int32_t* status, void* ws,
+                      size_t ws_bytes, void* hip_stream) {
+  if (!Q || !ns || !beta || !logz || !moments || !status || !ws)
+    return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  return run_moment_walk(batch, Q, nmax, ns, beta, logz, nullptr, nullptr, nullptr, moments, mean_energy, status,
+                         ws, ws_bytes, hip_stream);
 }
 
 }  // extern "C"

@@ -59,6 +59,7 @@ struct Inst {
   int32_t pad0;
   int64_t units;            // 2^tb work units
   int64_t unit_begin;       // first global unit index
+  int64_t local_off;        // tile value of the first unit (prefix-range solves; else 0)
   int64_t tab_off;          // first step of this instance's tables
   int64_t slot_off;         // first candidate-list slot
   int64_t slot_cap;         // candidate-list slots available

@@ -141,6 +141,45 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   if (lane == 0) status[b] = st;
 }
 
+// Merge of `count` lists of k_in (energy, mask) entries -- results of solves
+// over disjoint prefix ranges of one instance -- into the k best by (energy,
+// mask).  One wave: entries stream through 64 at a time, and those that beat
+// the current k-th are inserted into the wave's sorted list.  Energies pass
+// through float64 keys, exact for the int path's |E| <= 2^28 as well.
+template <class En>
+__global__ void __launch_bounds__(64) merge_topk_kernel(int count, int k_in, const En* ein, const uint64_t* min_,
+                                                        int k, En* eout, uint64_t* mout) {
+  const int lane = threadIdx.x;
+  double lkey = __builtin_inf();
+  uint64_t lmask = ~0ull;
+  const int64_t total = (int64_t)count * k_in;
+  for (int64_t base = 0; base < total; base += kWave) {
+    const int64_t e = base + lane;
+    double key = __builtin_inf();
+    uint64_t m = ~0ull;
+    if (e < total) {
+      const En x = ein[e];
+      if (x != Rescore<std::conditional_t<std::is_same_v<En, double>, float, int32_t>>::sentinel()) {
+        key = (double)x;
+        m = min_[e];
+      }
+    }
+    const double tk = readlane_f64(lkey, k - 1);
+    const uint64_t tm = readlane_u64(lmask, k - 1);
+    uint64_t bal = ballot(key < __builtin_inf() && before(key, m, tk, tm));
+    while (bal) {
+      const int src = __builtin_ctzll(bal);
+      bal &= bal - 1;
+      list_insert(lkey, lmask, readlane_f64(key, src), readlane_u64(m, src), k, lane);
+    }
+  }
+  if (lane < k) {
+    const bool fin = lkey < __builtin_inf();
+    eout[lane] = fin ? (En)lkey : Rescore<std::conditional_t<std::is_same_v<En, double>, float, int32_t>>::sentinel();
+    mout[lane] = fin ? lmask : ~0ull;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t stride, bool is_int, int k,
@@ -153,6 +192,21 @@ hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int6
   else
     hipLaunchKernelGGL(finalize_topk_kernel<float>, dim3(v.batch), dim3(64 * w), 0, s, v, (const float*)q, ldq,
                        stride, k, (double*)energies, masks, status);
+  return hipGetLastError();
+}
+
+}  // namespace qbf
+
+namespace qbf {
+
+hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, bool is_int, int k, void* eout,
+                             uint64_t* mout, hipStream_t s) {
+  if (is_int)
+    hipLaunchKernelGGL(merge_topk_kernel<int64_t>, dim3(1), dim3(64), 0, s, count, k_in, (const int64_t*)ein, min, k,
+                       (int64_t*)eout, mout);
+  else
+    hipLaunchKernelGGL(merge_topk_kernel<double>, dim3(1), dim3(64), 0, s, count, k_in, (const double*)ein, min, k,
+                       (double*)eout, mout);
   return hipGetLastError();
 }
 

@@ -42,6 +42,10 @@ struct PlanParams {
   int waves;     // waves of the persistent walk grid
   int lane_bits; // lane bits wanted (6 normally)
   int chunk_cap; // largest queue chunk (the planner picks <= this from the unit count)
+  // prefix-range solve (single instance): only masks whose top range_bits bits
+  // lie in [range_begin, range_end); range_bits = 0: every mask
+  int range_bits;
+  int64_t range_begin, range_end;
 };
 
 // plan: bit split, unit/table/slot offsets, counters.  ns == nullptr: one
@@ -66,6 +70,9 @@ hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int6
                                 int k, void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,
                                 hipStream_t s);
 
+// merge of top-k lists from disjoint prefix ranges of one instance (one wave).
+hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, bool is_int, int k, void* eout,
+                             uint64_t* mout, hipStream_t s);
 // log-partition: factor tables (after prep_tables), forward walk, finalize.
 hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,
                                  hipStream_t s);
@@ -75,7 +82,7 @@ hipError_t launch_finalize_logz(const Views& v, const float* beta, double* logz,
 hipError_t launch_walk_grad(const Views& v, const float* beta, const double* logz, int64_t total_waves,
                             int n_moments, hipStream_t s);
 hipError_t launch_finalize_grad(const Views& v, const float* q, const float* beta, const float* grad_logz,
-                                float* grad_q, float* grad_beta, int32_t* status, int n_moments,
-                                hipStream_t s);
+                                float* grad_q, float* grad_beta, double* moments, double* mean, int32_t* status,
+                                int n_moments, hipStream_t s);
 
 }  // namespace qbf

@@ -779,30 +779,35 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 }
 
 // One block per instance: sum the units' moments in order, scale, write.
+// Outputs (each optional): grad_q / grad_beta (adjoint of logZ, scaled by
+// grad_logz), moments (E_p[x_i x_j], float64) and mean (E_p[f]).
 __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta, const float* grad_logz,
-                                     float* grad_q, float* grad_beta, int32_t* status, int npairs) {
+                                     float* grad_q, float* grad_beta, double* moments, double* mean_out,
+                                     int32_t* status, int npairs) {
   __shared__ double red[256];
   const int b = blockIdx.x, tid = threadIdx.x;
   const Inst* I = &v.inst[b];
   const int nm = v.nmax;
   const int32_t st = I->status;
   const int n = I->n;
-  const double g = (double)grad_logz[b];
+  const double g = grad_logz ? (double)grad_logz[b] : 0.0;
   const double bt = (double)beta[b];
   const float* Q = q + (int64_t)b * nm * nm;
   double mean = 0.0;
   for (int idx = tid; idx < nm * nm; idx += blockDim.x) {
     const int i = idx / nm, j = idx % nm;
     float outv = 0.f;
+    double M = 0.0;
     if (st == 0 && i <= j && j < n) {
-      double M = 0.0;
       for (int64_t u = 0; u < I->units; ++u) M += v.part[(I->unit_begin + u) * npairs + pidx(n, i, j)];
       outv = (float)(g * -bt * M);
       mean += (double)Q[(int64_t)i * nm + j] * M;
     } else if (st != 0) {
       outv = __builtin_nanf("");
+      M = __builtin_nan("");
     }
-    grad_q[(int64_t)b * nm * nm + idx] = outv;
+    if (grad_q) grad_q[(int64_t)b * nm * nm + idx] = outv;
+    if (moments) moments[(int64_t)b * nm * nm + idx] = M;
   }
   red[tid] = mean;
   __syncthreads();
@@ -812,6 +817,7 @@ __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta,
   }
   if (tid == 0) {
     if (grad_beta) grad_beta[b] = st == 0 ? (float)(-g * red[0]) : __builtin_nanf("");
+    if (mean_out) mean_out[b] = st == 0 ? red[0] : __builtin_nan("");
     status[b] = st;
   }
 }
@@ -848,9 +854,10 @@ hipError_t launch_walk_grad(const Views& v, const float* beta, const double* log
 }
 
 hipError_t launch_finalize_grad(const Views& v, const float* q, const float* beta, const float* grad_logz,
-                                float* grad_q, float* grad_beta, int32_t* status, int n_moments, hipStream_t s) {
+                                float* grad_q, float* grad_beta, double* moments, double* mean, int32_t* status,
+                                int n_moments, hipStream_t s) {
   hipLaunchKernelGGL(finalize_grad_kernel, dim3(v.batch), dim3(256), 0, s, v, q, beta, grad_logz, grad_q,
-                     grad_beta, status, n_moments);
+                     grad_beta, moments, mean, status, n_moments);
   return hipGetLastError();
 }
 

@@ -30,10 +30,14 @@ __device__ Split split_bits(int n, const PlanParams& pp) {
   s.B = min(pp.inner, n);
   s.L = min(pp.lane_bits, n - s.B);
   const int rest = n - s.B - s.L;
-  s.no = max(0, min(pp.no_max, rest - pp.ub_min));
+  s.no = max(0, min(pp.no_max, rest - max(pp.ub_min, pp.range_bits)));
   s.tb = rest - s.no;
   s.units = int64_t(1) << s.tb;
   s.steps = int64_t(1) << s.no;
+  if (pp.range_bits > 0) {  // the prefix range as a contiguous range of units
+    const int shift = s.tb - pp.range_bits;
+    s.units = shift >= 0 ? (pp.range_end - pp.range_begin) << shift : 0;
+  }
   return s;
 }
 
@@ -90,6 +94,8 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
       I.tb = s.tb;
       I.units = s.units;
       I.unit_begin = cu;
+      I.local_off = pp.range_bits > 0 ? pp.range_begin << (s.tb - pp.range_bits) : 0;
+      if (pp.range_bits > s.tb) I.status = kErrArg;  // the host checks this; kept as a guard
       I.tab_off = cs;
       I.slot_off = csl;
       I.slot_cap = min<int64_t>(s.units, pp.waves);

@@ -127,7 +127,7 @@ struct WorkIter {
 // keep the compiler from proving the loads unclobbered, so force uniformity.
 struct InstU {
   int n, B, L, no, kp, status;
-  int64_t unit_begin, tab_off, slot_off, slot_cap;
+  int64_t unit_begin, local_off, tab_off, slot_off, slot_cap;
   double big;
 };
 
@@ -141,6 +141,7 @@ __device__ __forceinline__ InstU load_inst(const Views& v, int b) {
   r.kp = uniform_i32(I->kprime);
   r.status = uniform_i32(I->status);
   r.unit_begin = (int64_t)uniform_u64((uint64_t)I->unit_begin);
+  r.local_off = (int64_t)uniform_u64((uint64_t)I->local_off);
   r.tab_off = (int64_t)uniform_u64((uint64_t)I->tab_off);
   r.slot_off = (int64_t)uniform_u64((uint64_t)I->slot_off);
   r.slot_cap = (int64_t)uniform_u64((uint64_t)I->slot_cap);

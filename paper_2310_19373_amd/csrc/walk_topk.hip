@@ -275,7 +275,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
       cur = b;
     }
     const InstU I = load_inst(v, b);
-    if (I.status == 0) walk_unit<E>(v, b, I, u - (uint64_t)I.unit_begin, lkey, lmask, pub, myc, lane);
+    if (I.status == 0)
+      walk_unit<E>(v, b, I, u - (uint64_t)I.unit_begin + (uint64_t)I.local_off, lkey, lmask, pub, myc, lane);
   }
   if (cur >= 0) flush(v, cur, lkey, lmask, lane);
 }

@@ -89,3 +89,21 @@ def test_tuning_knobs_roundtrip():
     assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 0) == 0
     assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == old
     assert L.qubo_bf_set_tuning(99, 1) == -1
+
+
+def test_range_and_merge_argument_checks():
+    L = _lib.lib()
+    assert L.qubo_bf_range_workspace_size(40, 16, 0, 4) > 0
+    assert L.qubo_bf_range_workspace_size(40, 16, 0, 0) == 0      # p_bits >= 1
+    assert L.qubo_bf_range_workspace_size(40, 16, 0, 21) == 0     # p_bits <= 20
+    assert L.qubo_bf_range_workspace_size(14, 4, 1, 3) == 0       # p_bits <= n - 12
+    ws = 1 << 40
+    args = lambda pb, lo, hi: (FAKE, 30, 30, 0, 4, pb, lo, hi, FAKE, FAKE, FAKE, FAKE, ws, None)
+    assert L.qubo_bf_solve_range(*args(3, 2, 2)) == -1            # empty range
+    assert L.qubo_bf_solve_range(*args(3, 0, 9)) == -1            # beyond 2^p_bits
+    assert L.qubo_bf_solve_range(*args(3, -1, 2)) == -1
+    assert L.qubo_bf_solve_range(*args(19, 0, 1)) == -1           # p_bits > n - 12
+    assert L.qubo_bf_merge_topk(0, 4, FAKE, FAKE, 0, 4, FAKE, FAKE, None) == -1
+    assert L.qubo_bf_merge_topk(2, 4, FAKE, FAKE, 0, 65, FAKE, FAKE, None) == -1
+    assert L.qubo_bf_merge_topk(2, 4, None, FAKE, 0, 4, FAKE, FAKE, None) == -1
+    assert L.qubo_logz_moments(4, None, 8, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, ws, None) == -1
