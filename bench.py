@@ -134,6 +134,65 @@ def extra_single(dev, name, Q, k, dt, reps):
             "walk_ms": walk_s * 1e3, "walk_frac": states * ALG_OPS_PER_STATE / walk_s / PEAK_LANE_OPS}
 
 
+def extra_ranges(dev):
+    """The n=40 workload cut into 16 prefix ranges (resumable pieces) and
+    merged, against one full solve: the cost of chunking a long enumeration."""
+    import torch
+
+    from paper_2310_19373_amd import api, inputs
+
+    Q, xstar = inputs.single_n40_f32_planted()
+    Qd = torch.from_numpy(Q).to(dev)
+
+    def chunked():
+        parts = [api.solve_range(Qd, 16, 4, p, p + 1, check_lower=False) for p in range(16)]
+        return api.merge_topk(parts, 16)
+
+    e, m = chunked()
+    fe, fm = api.solve(Qd, 16)
+    t_chunked = _time(chunked, 2)
+    t_full = _time(lambda: api.solve(Qd, 16, check_lower=False), 2)
+    states = float(1 << 40)
+    return {"workload": "n=40 planted (seed 2), k=16, 16 prefix ranges of 2^36 states + merge",
+            "chunked_ms": t_chunked * 1e3, "full_ms": t_full * 1e3, "chunked_states_per_s": states / t_chunked,
+            "overhead": t_chunked / t_full - 1.0, "identical_to_full": bool(torch.equal(e, fe) and torch.equal(m, fm))}
+
+
+def extra_moments(dev):
+    """Second moments (marginals on the diagonal) and E_p[f] of the 768
+    (instance, beta) pairs: one batched logz_moments call (forward + moment
+    walk)."""
+    import torch
+
+    from paper_2310_19373_amd import api, inputs
+
+    Q, beta = inputs.logz_256x24()
+    Qt = torch.from_numpy(Q).to(dev)
+    bt = torch.from_numpy(beta).to(dev)
+    api.logz_moments(Qt, bt)
+    t = _time(lambda: api.logz_moments(Qt, bt), 3)
+    return {"workload": "768 (instance, beta) pairs, n=24 (seed 4): E_p[x_i x_j], E_p[f]",
+            "ms": t * 1e3, "states_per_s": 2 * 768 * float(1 << 24) / t}
+
+
+def extra_sample(dev, nsamples=256):
+    """Exact Boltzmann samples of the 768 (instance, beta) pairs, n=24: one
+    qubo_logz_sample call (forward enumeration + one wave per sample)."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19373_amd import api, inputs
+
+    Q, beta = inputs.logz_256x24()
+    Qt = torch.from_numpy(Q).to(dev)
+    bt = torch.from_numpy(beta).to(dev)
+    u = torch.from_numpy(np.random.default_rng(5).random((Q.shape[0], nsamples))).to(dev)
+    api.logz_sample(Qt, bt, u)
+    t = _time(lambda: api.logz_sample(Qt, bt, u), 3)
+    return {"workload": f"768 (instance, beta) pairs, n=24 (seed 4): {nsamples} exact samples each",
+            "ms": t * 1e3, "samples_per_s": Q.shape[0] * nsamples / t}
+
+
 def extra_batched(dev, plain_loop=True, tune=True):
     """Config 4: 4096 QUBOs, n uniform in [12, 28], k=1 -- one captured graph
     replay vs one qubo_bf_solve call per instance on the same stream."""
@@ -350,7 +409,8 @@ def main():
                                            _lib.QUBO_F32, 50),
             "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
                                            inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10),
-            "batched": extra_batched(dev), "logz": extra_logz(dev)}
+            "batched": extra_batched(dev), "logz": extra_logz(dev), "ranges": extra_ranges(dev),
+            "moments": extra_moments(dev), "sample": extra_sample(dev)}
     print(json.dumps(out), flush=True)
 
 

@@ -176,6 +176,33 @@ int qubo_logz_moments(int batch, const float* Q, int nmax, const int32_t* ns, co
                       const double* logz, double* moments, double* mean_energy, int32_t* status, void* ws,
                       size_t ws_bytes, void* hip_stream);
 
+/* Workspace bytes for qubo_logz_sample; 0 for invalid sizes. */
+size_t qubo_logz_sample_workspace_size(int batch, int nmax);
+
+/*
+ * Exact samples of p(x) = exp(-beta f(x) - logZ) (an extension with a plain
+ * definition): for each instance b and uniform u = u[b][s] in [0, 1), the
+ * mask m with F(m - 1) <= u < F(m), where F(m) = sum_{x <= m} p(x) runs over
+ * the masks in natural (integer) order -- inversion of the exact cumulative
+ * distribution.  The uniforms are inputs, so a caller owns the random stream
+ * and results are reproducible; values outside [0, 1) are clamped into it.
+ * Weights are evaluated in float32 per state and summed in float64, so a u
+ * within about 1e-5 of a boundary F(m) may return the neighbouring mask.
+ *   Q, ns, beta, nmax   as qubo_logz_fwd (nmax 1 .. 32)
+ *   nsamples  samples per instance, >= 1
+ *   u         device, [batch][nsamples] double
+ *   masks     device, [batch][nsamples] uint64 (all ones for an instance
+ *             whose status is not QUBO_OK)
+ *   logz      device, [batch] double: log Z, written as by qubo_logz_fwd
+ *   status    device, [batch]
+ *   ws        device workspace of qubo_logz_sample_workspace_size bytes
+ * One forward enumeration, then one wave per sample re-walks the sampled
+ * work unit's lane; all on hip_stream.
+ */
+int qubo_logz_sample(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, int nsamples,
+                     const double* u, uint64_t* masks, double* logz, int32_t* status, void* ws, size_t ws_bytes,
+                     void* hip_stream);
+
 /* ------------------------------------------------------------ utilities */
 
 /* Thread-local description of the last non-OK return (never NULL). */

@@ -49,6 +49,8 @@ SIGNATURES = {
     "qubo_logz_fwd": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_logz_bwd": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_logz_moments": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qubo_logz_sample_workspace_size": (_sz, [_i, _i]),
+    "qubo_logz_sample": (_i, [_i, _vp, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_last_error": (ctypes.c_char_p, []),
     "qubo_version": (ctypes.c_char_p, []),
     "qubo_bf_set_tuning": (_i, [_i, _i]),

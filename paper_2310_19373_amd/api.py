@@ -376,3 +376,54 @@ def marginals(Q, beta, ns=None):
     """E_p[x_i] under p(x) = exp(-beta f(x) - logZ): the diagonal of logz_moments."""
     _, mom, _ = logz_moments(Q, beta, ns)
     return torch.diagonal(mom, dim1=-2, dim2=-1)
+
+
+def logz_sample(Q, beta, u, ns=None):
+    """Exact samples of p(x) = exp(-beta f(x) - logZ) by inversion of the
+    cumulative distribution in natural mask order.
+
+    u: uniforms in [0, 1), shape [batch, nsamples] (or [nsamples] for a single
+    (n, n) Q), float64; the caller owns the random stream.  Returns (masks
+    [batch, nsamples] int64 -- bit i is x_i --, logz [batch] float64).
+    """
+    single = False
+    if not isinstance(Q, torch.Tensor):
+        Q = torch.as_tensor(np.asarray(Q))
+    if Q.ndim == 2:
+        Q = Q.unsqueeze(0)
+        single = True
+    if Q.dtype != torch.float32:
+        raise TypeError("Q must be float32")
+    Q = _as_device(Q, torch.float32)
+    _check_upper(Q)
+    dev = Q.device
+    batch, nmax = Q.shape[0], Q.shape[1]
+    if not isinstance(beta, torch.Tensor):
+        beta = torch.full((batch,), float(beta), dtype=torch.float32, device=dev)
+    beta = beta.to(device=dev, dtype=torch.float32).reshape(-1).expand(batch).contiguous()
+    nsd = torch.full((batch,), nmax, dtype=torch.int32, device=dev) if ns is None else _as_device(ns, torch.int32, dev)
+    if not isinstance(u, torch.Tensor):
+        u = torch.as_tensor(np.asarray(u, dtype=np.float64))
+    u = u.to(device=dev, dtype=torch.float64)
+    if single and u.ndim == 1:
+        u = u.unsqueeze(0)
+    if u.ndim != 2 or u.shape[0] != batch or u.shape[1] < 1:
+        raise ValueError(f"u must have shape [batch={batch}, nsamples]")
+    u = u.contiguous()
+    nsamples = u.shape[1]
+    L = _lib.lib()
+    nbytes = L.qubo_logz_sample_workspace_size(batch, nmax)
+    if nbytes == 0:
+        raise ValueError(f"unsupported sizes batch={batch}, nmax={nmax}")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    masks = torch.empty((batch, nsamples), dtype=torch.int64, device=dev)
+    lz = torch.empty(batch, dtype=torch.float64, device=dev)
+    status = torch.empty(batch, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _lib.check(L.qubo_logz_sample(batch, Q.data_ptr(), nmax, nsd.data_ptr(), beta.data_ptr(), nsamples,
+                                      u.data_ptr(), masks.data_ptr(), lz.data_ptr(), status.data_ptr(),
+                                      ws.data_ptr(), nbytes, _stream(dev)))
+    _raise_status(status)
+    if single:
+        return masks[0], lz[0]
+    return masks, lz

@@ -232,6 +232,7 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.etab = L.etab ? (void*)(p + L.etab) : nullptr;
   v.tref = L.tref ? (double*)(p + L.tref) : nullptr;
   v.dlist = L.dlist ? (uint64_t*)(p + L.dlist) : nullptr;
+  v.lanepart = nullptr;
   v.factor = L.etab && tuning().logz_factored > 0;
   v.seed_sweeps = tuning().seed_sweeps;
   v.batch = batch;
@@ -281,6 +282,16 @@ PlanParams grad_params() {
   pp.chunk_cap = clampi(tuning().chunk_batched, 1, 1 << 20);
   return pp;
 }
+
+// Sampling: the forward's plan with at most 8 outer bits (a lane's block
+// weights by outer value fit in LDS); per unit 1 + 64 + 1 doubles of
+// partial results (unit sum, lane sums, running sum).
+PlanParams sample_params() {
+  PlanParams pp = batched_params(1);
+  pp.no_max = 8;
+  return pp;
+}
+constexpr int64_t kSamplePart = 66;
 
 int logz_npairs(int nmax) { return nmax * (nmax + 1) / 2; }
 
@@ -587,6 +598,43 @@ int qubo_logz_moments(int batch, const float* Q, int nmax, const int32_t* ns, co
     return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
   return run_moment_walk(batch, Q, nmax, ns, beta, logz, nullptr, nullptr, nullptr, moments, mean_energy, status,
                          ws, ws_bytes, hip_stream);
+}
+
+size_t qubo_logz_sample_workspace_size(int batch, int nmax) {
+  if (batch < 1 || nmax < 1 || nmax > 32) return 0;
+  return make_layout(batch, nmax, sample_params(), kSamplePart, 0, true).total;
+}
+
+int qubo_logz_sample(int batch, const float* Q, int nmax, const int32_t* ns, const float* beta, int nsamples,
+                     const double* u, uint64_t* masks, double* logz, int32_t* status, void* ws, size_t ws_bytes,
+                     void* hip_stream) {
+  if (!Q || !ns || !beta || !u || !masks || !logz || !status || !ws)
+    return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (batch < 1) return fail(QUBO_ERR_INVALID_ARG, "batch=%d < 1", batch);
+  if (nmax < 1 || nmax > 32) return fail(QUBO_ERR_INVALID_ARG, "nmax=%d outside [1, 32]", nmax);
+  if (nsamples < 1) return fail(QUBO_ERR_INVALID_ARG, "nsamples=%d < 1", nsamples);
+  const size_t need = qubo_logz_sample_workspace_size(batch, nmax);
+  if (ws_bytes < need) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+  PlanParams pp = sample_params();
+  const Layout L = make_layout(batch, nmax, pp, kSamplePart, 0, true);
+  Views v = make_views(ws, L, batch, nmax);
+  const SplitH sh = split_host(nmax, pp);
+  const int64_t units_bound = (int64_t)batch << sh.tb;
+  v.lanepart = v.part + units_bound;
+  double* cum = v.part + units_bound * (kSamplePart - 1);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int waves = grid_waves();
+  pp.waves = waves;
+  const int64_t steps_bound = (int64_t)batch << sh.no;
+  HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
+  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
+  HIPCHK(launch_prep_lanes(v, false, s));
+  HIPCHK(launch_prep_tables(v, false, kInner, steps_bound, s));
+  HIPCHK(launch_prep_exp_tables(v, beta, kInner, steps_bound, s));
+  HIPCHK(launch_walk_exp(v, beta, waves, s));
+  HIPCHK(launch_finalize_logz(v, beta, logz, status, s));
+  HIPCHK(launch_sample(v, beta, logz, cum, nsamples, u, masks, waves, s));
+  return QUBO_OK;
 }
 
 }  // extern "C"

@@ -28,6 +28,7 @@ struct Views {
   double* tref;    // log-partition: min_j T'(g(t); j) + E_O(g(t)) per step, or null
   int factor;      // log-partition: 1 = factored form allowed
   uint64_t* dlist; // log-partition: units deferred to the direct-form pass, or null
+  double* lanepart;  // sampling: per unit and lane, log2 of the lane's sum (forward walk output), or null
   int seed_sweeps; // descent passes of the threshold seed (0: no seeding)
   int64_t umap_cap;
   int batch, nmax;
@@ -78,6 +79,10 @@ hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, 
                                  hipStream_t s);
 hipError_t launch_walk_exp(const Views& v, const float* beta, int waves, hipStream_t s);
 hipError_t launch_finalize_logz(const Views& v, const float* beta, double* logz, int32_t* status, hipStream_t s);
+// Boltzmann samples by inversion in natural mask order (after a forward walk
+// that wrote part and lanepart over a plan with at most 8 outer bits).
+hipError_t launch_sample(const Views& v, const float* beta, const double* logz, double* cum, int nsamples,
+                         const double* u, uint64_t* masks, int waves, hipStream_t s);
 // log-partition backward: moment walk (inner = 5) then assembly.
 hipError_t launch_walk_grad(const Views& v, const float* beta, const double* logz, int64_t total_waves,
                             int n_moments, hipStream_t s);

@@ -43,6 +43,7 @@ constexpr double kLog2e = 1.4426950408889634074;
 constexpr int kGradInner = 5;
 constexpr int kGradStates = 1 << kGradInner;
 constexpr int kGradMaxOuter = 8;
+constexpr int kSampleOuter = 8;  // outer bits of the sampling plan (block weights fit in LDS)
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -311,6 +312,7 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
     const double l = (valid && S > 0.0) ? log2(S) - bb * r : -__builtin_inf();
     const double lu = wave_lse2(l);
     if (lane == 0) gp(v.part)[u] = lu;
+    if (v.lanepart) gp(v.lanepart)[u * kWave + lane] = l;
   }
 }
 
@@ -822,6 +824,201 @@ __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta,
   }
 }
 
+// ------------------------------------------------------------ sampling
+
+// Inclusive prefix sum over the wave (double).
+__device__ __forceinline__ double wave_scan(double x, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// One wave per instance: running sums of the units' weights
+// 2^(part[u] - log2 Z), in unit order.
+__global__ void __launch_bounds__(kBlock) unit_cumsum_kernel(Views v, const double* logz, double* cum) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (b >= v.batch) return;
+  const Inst* I = &v.inst[b];
+  if (uniform_i32(I->status) != 0) return;
+  const int64_t units = (int64_t)uniform_u64((uint64_t)I->units);
+  const int64_t ub = (int64_t)uniform_u64((uint64_t)I->unit_begin);
+  const double lz2 = uniform_f64(logz[b]) * kLog2e;
+  double carry = 0.0;
+  for (int64_t u0 = 0; u0 < units; u0 += kWave) {
+    const int64_t u = u0 + lane;
+    const double w = u < units ? exp2(v.part[ub + u] - lz2) : 0.0;
+    const double incl = wave_scan(w, lane) + carry;
+    if (u < units) cum[ub + u] = incl;
+    carry = readlane_f64(incl, 63);
+  }
+}
+
+// First lane with a positive weight whose inclusive prefix exceeds t; if
+// rounding left t at or above the total, the last lane with a positive weight.
+__device__ __forceinline__ int pick_lane(double w, double incl, double t) {
+  const uint64_t over = ballot(incl > t && w > 0.0);
+  if (over) return __builtin_ctzll(over);
+  const uint64_t pos = ballot(w > 0.0);
+  return pos ? 63 - __builtin_clzll(pos) : 0;
+}
+
+// t in [0, wp) as the same fraction of a total recomputed as wc, below wc.
+__device__ __forceinline__ double rescale(double t, double wp, double wc) {
+  const double f = wp > 0.0 ? t / wp : 0.0;
+  return (f > 0.0 ? (f < 1.0 ? f : 0x1.fffffffffffffp-1) : 0.0) * wc;
+}
+
+// One wave per sample: inverts the cumulative distribution in natural mask
+// order, whose bit groups from the top are the tile bits (the work unit), the
+// lane bits, the outer bits and the inner bits.  The unit comes from the
+// per-unit running sums, the lane from the forward walk's per-lane sums, the
+// outer value from the chosen lane's block weights (one block per outer
+// value, lanes take the steps in parallel), the inner state from the chosen
+// block's 64 weights in float64.  The levels evaluate their weights in
+// different precisions, so the leftover of one level is carried to the next
+// as a fraction of the chosen entry's weight and rescaled by the next level's
+// own total: each level inverts its own distribution exactly, and the sampled
+// mask differs from the exact inverse only where u lies within the weights'
+// rounding of a boundary.
+__global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* beta, const double* logz,
+                                                       const double* cum, int nsamples, const double* uin,
+                                                       uint64_t* mout) {
+  __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
+  __shared__ double bw[kWavesPerBlock][1 << kSampleOuter];
+  __shared__ float cq[kWavesPerBlock][kInnerStates];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* myc = ctab[w];
+  double* myw = bw[w];
+  float* myq = cq[w];
+  const int64_t total = (int64_t)v.batch * nsamples;
+  for (int64_t id = (int64_t)blockIdx.x * kWavesPerBlock + w; id < total;
+       id += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int b = (int)(id / nsamples);
+    const InstU I = load_inst(v, b);
+    if (I.status != 0) {
+      if (lane == 0) mout[id] = ~0ull;
+      continue;
+    }
+    const int64_t units = (int64_t)uniform_u64((uint64_t)v.inst[b].units);
+    const double bb = fabs((double)beta[b]) * kLog2e;
+    const double lz2 = uniform_f64(logz[b]) * kLog2e;
+    double ur = uniform_f64(uin[id]);
+    ur = ur > 0.0 ? (ur < 1.0 ? ur : 0x1.fffffffffffffp-1) : 0.0;  // NaN -> 0
+    // 1. unit: the first whose running sum exceeds t
+    const double* cb = cum + I.unit_begin;
+    double t = ur * uniform_f64(cb[units - 1]);
+    int64_t lo = 0, hi = units - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (uniform_f64(cb[mid]) > t) hi = mid;
+      else lo = mid + 1;
+    }
+    const double c0 = lo > 0 ? uniform_f64(cb[lo - 1]) : 0.0;
+    double wp = uniform_f64(cb[lo]) - c0;  // weight of the chosen entry
+    t -= c0;
+    const uint64_t u = (uint64_t)(I.unit_begin + lo);
+    const uint64_t local = (uint64_t)lo;
+    // 2. lane
+    const double lw = exp2(gp(v.lanepart)[u * kWave + lane] - lz2);
+    const double lincl = wave_scan(lw, lane);
+    t = rescale(t, wp, readlane_f64(lincl, kWave - 1));
+    const int ls = pick_lane(lw, lincl, t);
+    t -= readlane_f64(lincl - lw, ls);
+    wp = readlane_f64(lw, ls);
+    // 3. outer value.  Lane ls's C' goes to LDS in the step tables' entry
+    // order (entry 4 (j mod 16) + j / 16 holds inner state j).
+    const bool valid = lane < (1 << I.L);
+    float C[kInnerStates];
+    const double EP = lane_init<float, kInnerStates>(v, b, I, local, valid, myc, lane, C);
+    float cj = 0.f;
+#pragma unroll
+    for (int j = 0; j < kInnerStates; ++j) {
+      const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(C[j]), ls));
+      if (lane == j) cj = x;
+    }
+    myq[4 * (lane & 15) + (lane >> 4)] = cj;
+    const double EPs = readlane_f64(EP, ls);
+    __builtin_amdgcn_wave_barrier();
+    const float nb = bb > 0.0 ? (float)-bb : -1e-30f;  // beta = 0: sentinels still weigh 0
+    const uint32_t steps = 1u << I.no;
+    const gptr<const f32x4> tab4 = gp((const f32x4*)v.tab) + I.tab_off * (kInnerStates / 4);
+    const gptr<const double> eod = gp((const double*)v.eod) + I.tab_off;
+    for (uint32_t st = lane; st < steps; st += kWave) {
+      const uint32_t o = (uint32_t)gray(st);
+      double K = EPs + eod[st];
+      for (int l = 0; l < I.no; ++l)
+        if ((o >> l) & 1) K += myc[l * kWave + ls];
+      const float cst = (float)(-bb * K - lz2);
+      const gptr<const f32x4> row = tab4 + (int64_t)st * (kInnerStates / 4);
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < kInnerStates / 4; ++q) {
+        const f32x4 tq = row[q];
+        acc[0] += exp2_fast(__builtin_fmaf(myq[4 * q + 0] + tq.x, nb, cst));
+        acc[1] += exp2_fast(__builtin_fmaf(myq[4 * q + 1] + tq.y, nb, cst));
+        acc[2] += exp2_fast(__builtin_fmaf(myq[4 * q + 2] + tq.z, nb, cst));
+        acc[3] += exp2_fast(__builtin_fmaf(myq[4 * q + 3] + tq.w, nb, cst));
+      }
+      myw[o] = (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    }
+    __builtin_amdgcn_wave_barrier();
+    // outer values in natural order: lane q sums values q*per .. q*per+per-1
+    const int per = steps >= kWave ? (int)(steps / kWave) : 1;
+    double part = 0.0;
+    for (int k = 0; k < per; ++k) {
+      const uint32_t o = (uint32_t)lane * per + k;
+      if (o < steps) part += myw[o];
+    }
+    const double pincl = wave_scan(part, lane);
+    t = rescale(t, wp, readlane_f64(pincl, kWave - 1));
+    const int q = pick_lane(part, pincl, t);
+    t -= readlane_f64(pincl - part, q);
+    uint32_t os = (uint32_t)q * per;
+    {
+      uint32_t last = os;
+      bool found = false;
+      for (int k = 0; k < per && !found; ++k) {
+        const uint32_t o = (uint32_t)q * per + k;
+        if (o >= steps) break;
+        const double x = myw[o];
+        if (x > 0.0) {
+          last = o;
+          if (t < x) {
+            os = o;
+            found = true;
+          } else {
+            t -= x;
+          }
+        }
+      }
+      if (!found) os = last;
+    }
+    os = (uint32_t)uniform_i32((int)os);
+    wp = myw[os];
+    // 4. inner state of block (ls, os), weights in float64
+    uint32_t ts = os;  // step with g(ts) = os
+    for (int sh = 1; sh < 32; sh <<= 1) ts ^= ts >> sh;
+    double Kb = EPs + uniform_f64(eod[ts]);
+    for (int l = 0; l < I.no; ++l)
+      if ((os >> l) & 1) Kb += myc[l * kWave + ls];
+    const float tj = gp((const float*)v.tab)[(I.tab_off + ts) * kInnerStates + 4 * (lane & 15) + (lane >> 4)];
+    const double e = (double)cj + (double)tj + Kb;
+    const double wj = cj < __builtin_inff() ? exp2(-bb * e - lz2) : 0.0;
+    const double jincl = wave_scan(wj, lane);
+    t = rescale(t, wp, readlane_f64(jincl, kWave - 1));
+    const int js = pick_lane(wj, jincl, t);
+    if (lane == 0) {
+      const uint64_t hi = ((local << I.L) | (uint64_t)ls) << I.no | (uint64_t)os;
+      mout[id] = (hi << I.B) | (uint64_t)js;
+    }
+    __builtin_amdgcn_wave_barrier();  // myq / myw / myc are rewritten by the next sample
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,
@@ -858,6 +1055,19 @@ hipError_t launch_finalize_grad(const Views& v, const float* q, const float* bet
                                 int n_moments, hipStream_t s) {
   hipLaunchKernelGGL(finalize_grad_kernel, dim3(v.batch), dim3(256), 0, s, v, q, beta, grad_logz, grad_q,
                      grad_beta, moments, mean, status, n_moments);
+  return hipGetLastError();
+}
+
+}  // namespace qbf
+
+namespace qbf {
+
+hipError_t launch_sample(const Views& v, const float* beta, const double* logz, double* cum, int nsamples,
+                         const double* u, uint64_t* masks, int waves, hipStream_t s) {
+  hipLaunchKernelGGL(unit_cumsum_kernel, dim3((v.batch + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
+                     v, logz, cum);
+  const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta, logz, cum, nsamples, u, masks);
   return hipGetLastError();
 }
 

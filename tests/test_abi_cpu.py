@@ -107,3 +107,20 @@ def test_range_and_merge_argument_checks():
     assert L.qubo_bf_merge_topk(2, 4, FAKE, FAKE, 0, 65, FAKE, FAKE, None) == -1
     assert L.qubo_bf_merge_topk(2, 4, None, FAKE, 0, 4, FAKE, FAKE, None) == -1
     assert L.qubo_logz_moments(4, None, 8, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, ws, None) == -1
+
+
+def test_sample_argument_checks():
+    L = _lib.lib()
+    assert L.qubo_logz_sample_workspace_size(16, 32) > L.qubo_logz_sample_workspace_size(16, 20) > 0
+    assert L.qubo_logz_sample_workspace_size(0, 8) == 0
+    assert L.qubo_logz_sample_workspace_size(4, 33) == 0
+    ws = 1 << 40
+    args = lambda **kw: tuple(kw.get(k, d) for k, d in (
+        ("batch", 4), ("Q", FAKE), ("nmax", 8), ("ns", FAKE), ("beta", FAKE), ("nsamples", 16), ("u", FAKE),
+        ("masks", FAKE), ("logz", FAKE), ("status", FAKE), ("ws", FAKE), ("ws_bytes", ws), ("stream", None)))
+    assert L.qubo_logz_sample(*args(nsamples=0)) == -1
+    assert L.qubo_logz_sample(*args(u=None)) == -1
+    assert L.qubo_logz_sample(*args(logz=None)) == -1
+    assert L.qubo_logz_sample(*args(nmax=33)) == -1
+    assert L.qubo_logz_sample(*args(batch=0)) == -1
+    assert L.qubo_logz_sample(*args(ws_bytes=64)) == -3
