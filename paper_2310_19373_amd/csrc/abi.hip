@@ -318,9 +318,8 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   HIPCHK(launch_prep_inst(v, Q, ldq, stride, is_int, kInner, s));
   HIPCHK(launch_prep_lanes(v, is_int, s));
   // single small instances: the walk is shorter than the seed's latency.  A
-  // prefix-range solve takes no seed: its backing states could lie outside
-  // the range.
-  if (pp.range_bits == 0 && (ns != nullptr || n_single > 22)) HIPCHK(launch_seed(v, is_int, s));
+  // prefix-range solve seeds inside its range (the planner's seed_fix).
+  if (ns != nullptr || n_single > 22) HIPCHK(launch_seed(v, is_int, s));
   HIPCHK(launch_prep_tables(v, is_int, kInner, steps_hint, s));
   {
     ProfScope ps("walk_topk", s);

@@ -56,7 +56,7 @@ struct Inst {
   int32_t n, B, L, no, tb;  // bit split (see above)
   int32_t kprime;           // candidate list length
   int32_t status;           // device-detected status, 0 = OK
-  int32_t pad0;
+  int32_t seed_fix;         // top bits the threshold seed keeps at the range's first prefix
   int64_t units;            // 2^tb work units
   int64_t unit_begin;       // first global unit index
   int64_t local_off;        // tile value of the first unit (prefix-range solves; else 0)

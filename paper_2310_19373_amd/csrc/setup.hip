@@ -95,6 +95,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
       I.units = s.units;
       I.unit_begin = cu;
       I.local_off = pp.range_bits > 0 ? pp.range_begin << (s.tb - pp.range_bits) : 0;
+      I.seed_fix = pp.range_bits > 0 ? pp.range_bits : 0;
       if (pp.range_bits > s.tb) I.status = kErrArg;  // the host checks this; kept as a guard
       I.tab_off = cs;
       I.slot_off = csl;
@@ -261,7 +262,10 @@ __device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
 // one-flip neighbours are n + 1 distinct states, so the K'-th smallest of their
 // values bounds the instance's K'-th smallest value from above.  Published with
 // the float filter's error margin, the bound discards nothing the walk would
-// keep; it only spares each wave the replays of its cold start.
+// keep; it only spares each wave the replays of its cold start.  A prefix-range
+// solve keeps its top seed_fix bits at the range's first prefix and descends
+// over the free bits only, so that x* and its free-bit neighbours lie in the
+// range and bound the range's K'-th smallest value.
 //
 // With S the symmetric off-diagonal part and d the diagonal,
 //   f(x) = sum_i x_i (d_i + h_i(x) / 2),  f(x ^ e_i) = f(x) + (1 - 2 x_i)(d_i + h_i(x)),
@@ -273,7 +277,8 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   const Inst* I = &v.inst[b];
   if (I->status != 0) return;
   const int n = I->n, kp = I->kprime, nm = v.nmax;
-  if (kp > n + 1) return;
+  const int fix = I->seed_fix, nf = n - fix;  // free (searched) bits: [0, nf)
+  if (kp > nf + 1) return;
   const int np = (n + 3) & ~3;
   // exact (W) and float32 copies of S with zero diagonal and padded rows, and d
   W* sw = (W*)seed_lds;
@@ -292,14 +297,15 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
     df[i] = (float)dw[i];
   }
   __syncthreads();
-  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  uint64_t x = lane == 0 ? 0 : (mix64(((uint64_t)b << 6) | (uint64_t)lane) & all);
+  const uint64_t free = nf >= 64 ? ~0ull : ((1ull << nf) - 1);
+  const uint64_t base = fix > 0 ? ((uint64_t)I->local_off >> (I->tb - fix)) << nf : 0;
+  uint64_t x = base | (lane == 0 ? 0 : (mix64(((uint64_t)b << 6) | (uint64_t)lane) & free));
   // descent in float32 (any states back the bound, so neither convergence nor
   // exact deltas matter here): at most `sweeps` passes over the bits
   const int sweeps = v.seed_sweeps < 4 * n ? v.seed_sweeps : 4 * n;
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     bool moved = false;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < nf; ++i) {
       const float g = df[i] + field(sf + i * np, np, x);
       if ((((x >> i) & 1) ? -g : g) < 0.f) {
         x ^= 1ull << i;
@@ -329,10 +335,10 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   else tot = (W)uniform_u64((uint64_t)tot) / 2;  // even: 2 sum_i x_i d_i + 2 sum_{i<j} S_ij x_i x_j
   key = __builtin_inf();
   mask = ~0ull;
-  if (lane < n) {
+  if (lane < nf) {
     mask = xs ^ (1ull << lane);
     key = (double)(((xs >> lane) & 1) ? tot - gi : tot + gi);
-  } else if (lane == n) {
+  } else if (lane == nf) {
     mask = xs;
     key = (double)tot;
   }

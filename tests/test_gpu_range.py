@@ -71,3 +71,17 @@ def test_n40_in_four_ranges_equals_full_solve(gpu_lib):
     assert int(_np(mm)[0]) == xstar
     assert _u64(_np(mm)) == _u64(_np(fm))
     assert np.array_equal(_np(me), _np(fe))
+
+
+@pytest.mark.parametrize("dtype,k,lo,hi", [("f32", 8, 1, 2), ("f32", 16, 3, 7), ("i32", 8, 9, 16),
+                                          ("i32", 40, 0, 1)])
+def test_seeded_ranges_against_oracle(gpu_lib, dtype, k, lo, hi):
+    # n > 22: the threshold seed runs, confined to the range's first prefix
+    # (k = 40 leaves more candidates than the 22 free bits back: no seed)
+    n, pb = 26, 4
+    Q = inputs.random_f32(n, 510) if dtype == "f32" else inputs.random_i32(n, 511, -30, 30)
+    print(f"seeded range {dtype} k={k} [{lo},{hi}) of 2^{pb}", flush=True)
+    e, m = api.solve_range(Q, k, pb, lo, hi)
+    E, M = oracle.topk(Q, k, lo=lo << (n - pb), hi=hi << (n - pb))
+    assert _u64(_np(m)) == _u64(M)
+    assert np.array_equal(_np(e), E)
