@@ -1,8 +1,9 @@
 """CPU oracle (test infrastructure only).
 
 Plain, slow, obviously correct evaluation of the QUBO objective of Eq. 1 in
-natural binary order, in float64 (float Q) or int64 (integer Q), plus the
-log-partition function and its gradient defined directly from their sums.
+natural binary order, in float64 (float32 / float64 Q) or int64 (int32 / int64
+Q), plus the log-partition function and its gradient defined directly from
+their sums.
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package; the product path never does.  It shares no code with the HIP
 library; the only common module is the seeded input generator.
@@ -50,6 +51,18 @@ def _load():
     lib.qo_topk_f32.restype = ctypes.c_int
     lib.qo_topk_i32.argtypes = [c_i, ctypes.c_int, i64, u64, u64, ctypes.c_int, c_l, c_u, ctypes.c_int]
     lib.qo_topk_i32.restype = ctypes.c_int
+    lib.qo_energy_f64.argtypes = [c_d, ctypes.c_int, i64, u64]
+    lib.qo_energy_f64.restype = ctypes.c_double
+    lib.qo_energy_i64.argtypes = [c_l, ctypes.c_int, i64, u64]
+    lib.qo_energy_i64.restype = ctypes.c_int64
+    lib.qo_energies_f64.argtypes = [c_d, ctypes.c_int, i64, c_u, i64, c_d]
+    lib.qo_energies_f64.restype = None
+    lib.qo_energies_i64.argtypes = [c_l, ctypes.c_int, i64, c_u, i64, c_l]
+    lib.qo_energies_i64.restype = None
+    lib.qo_topk_f64.argtypes = [c_d, ctypes.c_int, i64, u64, u64, ctypes.c_int, c_d, c_u, ctypes.c_int]
+    lib.qo_topk_f64.restype = ctypes.c_int
+    lib.qo_topk_i64.argtypes = [c_l, ctypes.c_int, i64, u64, u64, ctypes.c_int, c_l, c_u, ctypes.c_int]
+    lib.qo_topk_i64.restype = ctypes.c_int
     lib.qo_logz_f32.argtypes = [c_f, ctypes.c_int, i64, ctypes.c_double, c_d, ctypes.c_int]
     lib.qo_logz_f32.restype = ctypes.c_double
     lib.qo_grad_f32.argtypes = [c_f, ctypes.c_int, i64, ctypes.c_double, ctypes.c_double, c_d, ctypes.c_int]
@@ -75,33 +88,43 @@ def _prep(Q):
     raise TypeError("Q must be float32 or int32")
 
 
+# element type -> (C element, C result, result dtype, name suffix, sentinel)
+_KINDS = {
+    np.dtype(np.float32): (ctypes.c_float, ctypes.c_double, np.float64, "f32"),
+    np.dtype(np.int32): (ctypes.c_int32, ctypes.c_int64, np.int64, "i32"),
+    np.dtype(np.float64): (ctypes.c_double, ctypes.c_double, np.float64, "f64"),
+    np.dtype(np.int64): (ctypes.c_int64, ctypes.c_int64, np.int64, "i64"),
+}
+
+
+def _kind(Q):
+    Q = np.ascontiguousarray(Q)
+    if Q.ndim != 2 or Q.shape[0] != Q.shape[1]:
+        raise ValueError("Q must be square")
+    if Q.dtype not in _KINDS:
+        raise TypeError("Q must be float32, int32, float64 or int64")
+    return Q, _KINDS[Q.dtype]
+
+
 def max_threads() -> int:
     return _load().qo_max_threads()
 
 
 def energy(Q, mask: int):
     """f_Q(x) for the mask (bit i = x_i): float (f64) or int (int64)."""
-    Q, isf = _prep(Q)
+    Q, (ce, _, _, sfx) = _kind(Q)
     lib = _load()
     n = Q.shape[0]
-    if isf:
-        return lib.qo_energy_f32(_ptr(Q, ctypes.c_float), n, n, mask)
-    return lib.qo_energy_i32(_ptr(Q, ctypes.c_int32), n, n, mask)
+    return getattr(lib, "qo_energy_" + sfx)(_ptr(Q, ce), n, n, mask)
 
 
 def energies(Q, masks):
-    Q, isf = _prep(Q)
+    Q, (ce, cr, rt, sfx) = _kind(Q)
     lib = _load()
     n = Q.shape[0]
     m = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
-    if isf:
-        out = np.empty(m.shape, dtype=np.float64)
-        lib.qo_energies_f32(_ptr(Q, ctypes.c_float), n, n, _ptr(m, ctypes.c_uint64), m.size,
-                            _ptr(out, ctypes.c_double))
-    else:
-        out = np.empty(m.shape, dtype=np.int64)
-        lib.qo_energies_i32(_ptr(Q, ctypes.c_int32), n, n, _ptr(m, ctypes.c_uint64), m.size,
-                            _ptr(out, ctypes.c_int64))
+    out = np.empty(m.shape, dtype=rt)
+    getattr(lib, "qo_energies_" + sfx)(_ptr(Q, ce), n, n, _ptr(m, ctypes.c_uint64), m.size, _ptr(out, cr))
     return out
 
 
@@ -111,20 +134,15 @@ def topk(Q, k: int, lo: int = 0, hi: int | None = None, threads: int = 0):
     Returns (energies float64|int64 [k], masks uint64 [k]); missing slots carry
     +inf / INT64_MAX and mask 2^64-1.
     """
-    Q, isf = _prep(Q)
+    Q, (ce, cr, rt, sfx) = _kind(Q)
     lib = _load()
     n = Q.shape[0]
     if hi is None:
         hi = 1 << n
     M = np.empty(k, dtype=np.uint64)
-    if isf:
-        E = np.empty(k, dtype=np.float64)
-        rc = lib.qo_topk_f32(_ptr(Q, ctypes.c_float), n, n, lo, hi, k, _ptr(E, ctypes.c_double),
-                             _ptr(M, ctypes.c_uint64), threads)
-    else:
-        E = np.empty(k, dtype=np.int64)
-        rc = lib.qo_topk_i32(_ptr(Q, ctypes.c_int32), n, n, lo, hi, k, _ptr(E, ctypes.c_int64),
-                             _ptr(M, ctypes.c_uint64), threads)
+    E = np.empty(k, dtype=rt)
+    rc = getattr(lib, "qo_topk_" + sfx)(_ptr(Q, ce), n, n, lo, hi, k, _ptr(E, cr), _ptr(M, ctypes.c_uint64),
+                                         threads)
     if rc != 0:
         raise ValueError("oracle topk: bad arguments")
     return E, M

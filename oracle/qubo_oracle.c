@@ -20,7 +20,8 @@
  *   - the zero vector is a candidate with value 0 (Sec. 2.1, Sec. 3 code);
  *   - ties are broken by the lower natural mask, i.e. candidates are ordered
  *     lexicographically by (energy, mask);
- *   - float Q is widened exactly to double; integer Q to int64.
+ *   - float Q is widened exactly to double; integer Q to int64 (float64 and
+ *     int64 Q are used as stored).
  *
  * Summation order of one energy (the canonical order, used for bitwise
  * comparison of rescored values): i ascending; for each i with x_i = 1 the row
@@ -104,6 +105,64 @@ void qo_energies_i32(const int32_t *Q, int n, int64_t ldq, const uint64_t *masks
 {
     for (int64_t c = 0; c < count; ++c)
         out[c] = energy_i(Q, n, ldq, masks[c]);
+}
+
+/*
+ * float64 and int64 Q: the same definition and summation order.  float64 Q is
+ * used as stored; int64 sums are exact while sum |Q_ij| < 2^63.
+ */
+static double energy_d(const double *Q, int n, int64_t ldq, uint64_t mask)
+{
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!((mask >> i) & 1u))
+            continue;
+        double row = Q[(int64_t)i * ldq + i];
+        for (int j = i + 1; j < n; ++j)
+            if ((mask >> j) & 1u)
+                row += Q[(int64_t)i * ldq + j];
+        total += row;
+    }
+    return total;
+}
+
+static int64_t energy_l(const int64_t *Q, int n, int64_t ldq, uint64_t mask)
+{
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!((mask >> i) & 1u))
+            continue;
+        int64_t row = Q[(int64_t)i * ldq + i];
+        for (int j = i + 1; j < n; ++j)
+            if ((mask >> j) & 1u)
+                row += Q[(int64_t)i * ldq + j];
+        total += row;
+    }
+    return total;
+}
+
+double qo_energy_f64(const double *Q, int n, int64_t ldq, uint64_t mask)
+{
+    return energy_d(Q, n, ldq, mask);
+}
+
+int64_t qo_energy_i64(const int64_t *Q, int n, int64_t ldq, uint64_t mask)
+{
+    return energy_l(Q, n, ldq, mask);
+}
+
+void qo_energies_f64(const double *Q, int n, int64_t ldq, const uint64_t *masks,
+                     int64_t count, double *out)
+{
+    for (int64_t c = 0; c < count; ++c)
+        out[c] = energy_d(Q, n, ldq, masks[c]);
+}
+
+void qo_energies_i64(const int64_t *Q, int n, int64_t ldq, const uint64_t *masks,
+                     int64_t count, int64_t *out)
+{
+    for (int64_t c = 0; c < count; ++c)
+        out[c] = energy_l(Q, n, ldq, masks[c]);
 }
 
 /* ----------------------------------------------------------- top-k lists */
@@ -220,6 +279,73 @@ int qo_topk_i32(const int32_t *Q, int n, int64_t ldq, uint64_t lo, uint64_t hi, 
         chunk(lo, span, t, nt, &a, &b);
         for (uint64_t x = a; x < b; ++x)
             insert_i(E + (size_t)t * k, M + (size_t)t * k, k, &len[t], energy_i(Q, n, ldq, x), x);
+    }
+    int outlen = 0;
+    for (int i = 0; i < k; ++i) {
+        E_out[i] = INT64_MAX;
+        M_out[i] = ~0ull;
+    }
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < len[t]; ++i)
+            insert_i(E_out, M_out, k, &outlen, E[(size_t)t * k + i], M[(size_t)t * k + i]);
+    free(E);
+    free(M);
+    free(len);
+    return QO_OK;
+}
+
+/* The same selection for float64 and int64 Q. */
+int qo_topk_f64(const double *Q, int n, int64_t ldq, uint64_t lo, uint64_t hi, int k,
+                double *E_out, uint64_t *M_out, int nthreads)
+{
+    if (n < 1 || n > 63 || k < 1 || lo > hi || hi > (1ull << n))
+        return QO_ERR_ARG;
+    int T = threads_for(nthreads);
+    double *E = (double *)malloc(sizeof(double) * (size_t)T * k);
+    uint64_t *M = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)T * k);
+    int *len = (int *)calloc((size_t)T, sizeof(int));
+    uint64_t span = hi - lo;
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        int nt = omp_get_num_threads();
+        uint64_t a, b;
+        chunk(lo, span, t, nt, &a, &b);
+        for (uint64_t x = a; x < b; ++x)
+            insert_d(E + (size_t)t * k, M + (size_t)t * k, k, &len[t], energy_d(Q, n, ldq, x), x);
+    }
+    int outlen = 0;
+    for (int i = 0; i < k; ++i) {
+        E_out[i] = INFINITY;
+        M_out[i] = ~0ull;
+    }
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < len[t]; ++i)
+            insert_d(E_out, M_out, k, &outlen, E[(size_t)t * k + i], M[(size_t)t * k + i]);
+    free(E);
+    free(M);
+    free(len);
+    return QO_OK;
+}
+
+int qo_topk_i64(const int64_t *Q, int n, int64_t ldq, uint64_t lo, uint64_t hi, int k,
+                int64_t *E_out, uint64_t *M_out, int nthreads)
+{
+    if (n < 1 || n > 63 || k < 1 || lo > hi || hi > (1ull << n))
+        return QO_ERR_ARG;
+    int T = threads_for(nthreads);
+    int64_t *E = (int64_t *)malloc(sizeof(int64_t) * (size_t)T * k);
+    uint64_t *M = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)T * k);
+    int *len = (int *)calloc((size_t)T, sizeof(int));
+    uint64_t span = hi - lo;
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        int nt = omp_get_num_threads();
+        uint64_t a, b;
+        chunk(lo, span, t, nt, &a, &b);
+        for (uint64_t x = a; x < b; ++x)
+            insert_i(E + (size_t)t * k, M + (size_t)t * k, k, &len[t], energy_l(Q, n, ldq, x), x);
     }
     int outlen = 0;
     for (int i = 0; i < k; ++i) {

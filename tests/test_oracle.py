@@ -440,3 +440,73 @@ def test_grad_central_finite_differences_and_richardson():
         errs[h] = e
     assert errs[1e-3] < 1e-5
     assert errs[5e-4] < errs[1e-3] / 2.5
+
+
+# ------------------------------------------------ float64 and int64 inputs
+
+def _fraction_energy(Q, mask):
+    """Eq. 1 in exact rational arithmetic over the stored float64 values."""
+    from fractions import Fraction
+
+    n = Q.shape[0]
+    x = [(mask >> i) & 1 for i in range(n)]
+    return sum((Fraction(float(Q[i, j])) for i in range(n) for j in range(i, n) if x[i] and x[j]), Fraction(0))
+
+
+def test_f64_energy_within_rounding_of_exact_sum():
+    # Eq. 1 on float64 Q: the oracle's float64 sum lies within n^2 roundings of
+    # the exact rational value; values are not float32-representable
+    rng = np.random.default_rng(71)
+    n = 9
+    Q = np.triu(rng.standard_normal((n, n)) * 1e3 + 1e-7)
+    tol = n * n * 2.0**-53 * float(np.abs(Q).sum())
+    E = oracle.energies(Q, np.arange(1 << n, dtype=np.uint64))
+    for mask in range(1 << n):
+        assert abs(E[mask] - float(_fraction_energy(Q, mask))) <= tol
+    assert E[0] == 0.0
+
+
+def test_f64_reduces_to_f32_on_float32_values():
+    # float32 values widened to float64 are the same numbers: both input types
+    # give bitwise the same energies and the same selection
+    Q32 = inputs.random_f32(12, 72)
+    Q64 = Q32.astype(np.float64)
+    masks = np.arange(1 << 12, dtype=np.uint64)
+    assert np.array_equal(oracle.energies(Q64, masks), oracle.energies(Q32, masks))
+    e32, m32 = oracle.topk(Q32, 9)
+    e64, m64 = oracle.topk(Q64, 9)
+    assert np.array_equal(e32, e64) and np.array_equal(m32, m64)
+
+
+@pytest.mark.parametrize("n,k", [(1, 2), (5, 32), (6, 5), (10, 12)])
+def test_topk_f64_and_i64_equal_bruteforce(n, k):
+    # Sec. 3 naive enumeration with Python's exact integers (values far beyond
+    # int32) and exact rationals: the k smallest by (energy, mask)
+    rng = np.random.default_rng(73 + n)
+    Qi = np.triu(rng.integers(-2**40, 2**40, (n, n), dtype=np.int64))
+    vals = [py_energy(Qi, m) for m in range(1 << n)]
+    E, M = oracle.topk(Qi, k)
+    ref = sorted((v, m) for m, v in enumerate(vals))[:k]
+    assert [int(e) for e in E[:len(ref)]] == [v for v, _ in ref]
+    assert [int(m) for m in M[:len(ref)]] == [m for _, m in ref]
+    Qf = np.triu(rng.standard_normal((n, n)) * 7.3)
+    exact = [_fraction_energy(Qf, m) for m in range(1 << n)]
+    E, M = oracle.topk(Qf, k)
+    ref = sorted((v, m) for m, v in enumerate(exact))[:k]
+    assert [int(m) for m in M[:len(ref)]] == [m for _, m in ref]
+    assert all(abs(e - float(v)) <= 1e-12 * max(1.0, abs(float(v))) for e, (v, _) in zip(E, ref))
+    if k > 1 << n:
+        assert np.isinf(E[1 << n:]).all()
+
+
+def test_i64_matches_i32_on_int32_values_and_diagonal_closed_form():
+    Q32 = inputs.random_i32(11, 74)
+    e32, m32 = oracle.topk(Q32, 7)
+    e64, m64 = oracle.topk(Q32.astype(np.int64), 7)
+    assert np.array_equal(e32, e64) and np.array_equal(m32, m64)
+    # diagonal Q: the minimum is the sum of the negative diagonal entries, at the
+    # mask of those entries (zeros stay 0)
+    d = np.array([5 * 2**40, -3 * 2**41, 0, -7, 2**45, -1], dtype=np.int64)
+    E, M = oracle.topk(np.diag(d), 1)
+    assert int(E[0]) == int(d[d < 0].sum())
+    assert int(M[0]) == sum(1 << i for i in range(d.size) if d[i] < 0)

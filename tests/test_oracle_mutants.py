@@ -28,6 +28,11 @@ MUTANTS = {
     "logz_sign": ("double w = exp(-beta * e - M);", "double w = exp(beta * e - M);"),
     "grad_misses_diagonal": ("for (int j = i; j < n; ++j)", "for (int j = i + 1; j < n; ++j)"),
     "grad_sign": ("G[e] = (i <= j) ? -beta * nsum_val(&s) : 0.0;", "G[e] = (i <= j) ? beta * nsum_val(&s) : 0.0;"),
+    "f64_drop_diagonal": ("double row = Q[(int64_t)i * ldq + i];", "double row = 0.0;"),
+    "f64_transposed_operand": ("row += Q[(int64_t)i * ldq + j];", "row += Q[(int64_t)j * ldq + i];"),
+    "i64_drop_diagonal": ("int64_t row = Q[(int64_t)i * ldq + i];", "int64_t row = 0;"),
+    "f64_topk_skips_a_state": ("for (uint64_t x = a; x < b; ++x)\n            insert_d(E + (size_t)t * k, M + (size_t)t * k, k, &len[t], energy_d(",
+                               "for (uint64_t x = a + 1; x < b; ++x)\n            insert_d(E + (size_t)t * k, M + (size_t)t * k, k, &len[t], energy_d("),
 }
 
 PINS = [
@@ -41,6 +46,9 @@ PINS = [
     pins.test_logz_closed_forms,
     pins.test_grad_closed_forms,
     pins.test_grad_against_bruteforce_moments,
+    pins.test_f64_energy_within_rounding_of_exact_sum,
+    lambda: pins.test_topk_f64_and_i64_equal_bruteforce(5, 32),
+    pins.test_i64_matches_i32_on_int32_values_and_diagonal_closed_form,
 ]
 
 
