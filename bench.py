@@ -98,10 +98,11 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def extra_single(dev, name, Q, k, dt, reps):
-    """One full qubo_bf_solve per call on a smaller configuration; states/s of
-    the call and the walk kernel's VALU roofline fraction (1.5 lane-ops per
-    state, HIP events around the walk launch)."""
+def extra_single(dev, name, Q, k, dt, reps, ops_per_state=ALG_OPS_PER_STATE):
+    """One full qubo_bf_solve per call on another configuration; states/s of
+    the call and the walk kernel's VALU roofline fraction (ops_per_state
+    lane-ops per state: 1.5 for the float32 / int32 walks, 3 for the float64
+    walk; HIP events around the walk launch)."""
     import torch
 
     from paper_2310_19373_amd import _lib
@@ -111,7 +112,7 @@ def extra_single(dev, name, Q, k, dt, reps):
     L = _lib.lib()
     ws_bytes = L.qubo_bf_workspace_size(n, k, dt)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=dev)
+    en = torch.empty(k, dtype=torch.float64 if dt in (_lib.QUBO_F32, _lib.QUBO_F64) else torch.int64, device=dev)
     mk = torch.empty(k, dtype=torch.int64, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
@@ -131,7 +132,7 @@ def extra_single(dev, name, Q, k, dt, reps):
     states = float(1 << n)
     walk_s = wms / 1e3 / max(wn, 1)
     return {"workload": name, "states": states, "ms_per_call": t * 1e3, "states_per_s": states / t,
-            "walk_ms": walk_s * 1e3, "walk_frac": states * ALG_OPS_PER_STATE / walk_s / PEAK_LANE_OPS}
+            "walk_ms": walk_s * 1e3, "walk_frac": states * ops_per_state / walk_s / PEAK_LANE_OPS}
 
 
 def extra_ranges(dev):
@@ -409,6 +410,9 @@ def main():
                                            _lib.QUBO_F32, 50),
             "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
                                            inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10),
+            "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64, k=16, float64 walk",
+                                           inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64,
+                                           3, ops_per_state=3.0),
             "batched": extra_batched(dev), "logz": extra_logz(dev), "ranges": extra_ranges(dev),
             "moments": extra_moments(dev), "sample": extra_sample(dev)}
     print(json.dumps(out), flush=True)

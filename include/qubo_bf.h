@@ -40,6 +40,13 @@
  * the outputs are still written and `status` is QUBO_ERR_UNCERTAIN.
  * Integer semantics: int32 Q, exact int32 walk (requires sum_{i<=j} |Q_ij| <=
  * 2^28, else status QUBO_ERR_RANGE), int64 energies, bit-exact results.
+ * Wide types: float64 Q (QUBO_F64) and int64 Q (QUBO_I64) are enumerated in
+ * float64 arithmetic (about twice the time of the float32 walk).  QUBO_F64
+ * rescores in float64 and certifies like QUBO_F32 with a bound of
+ * 2^-36 sum |Q_ij| (0 for integer-valued Q with sum |Q_ij| <= 2^50);
+ * QUBO_I64 is exact and bit-exact for sum |Q_ij| <= 2^50 (else status
+ * QUBO_ERR_RANGE), with int64 energies -- the path for integer Q whose sum
+ * exceeds the int32 walk's 2^28.
  */
 #ifndef QUBO_BF_H
 #define QUBO_BF_H
@@ -51,7 +58,7 @@
 extern "C" {
 #endif
 
-typedef enum { QUBO_F32 = 0, QUBO_I32 = 1 } qubo_dtype;
+typedef enum { QUBO_F32 = 0, QUBO_I32 = 1, QUBO_F64 = 2, QUBO_I64 = 3 } qubo_dtype;
 
 enum {
   QUBO_OK = 0,
@@ -60,7 +67,7 @@ enum {
   QUBO_ERR_WORKSPACE = -3,   /* ws_bytes smaller than the workspace query */
   QUBO_ERR_HIP = -4,         /* a HIP launch or runtime call failed */
   QUBO_ERR_UNCERTAIN = -5,   /* float certificate failed (device status) */
-  QUBO_ERR_RANGE = -6,       /* int32 Q with sum |Q_ij| > 2^28 (device status) */
+  QUBO_ERR_RANGE = -6,       /* integer Q whose sum |Q_ij| exceeds its walk's bound (device status) */
   QUBO_ERR_OVERFLOW = -7     /* internal slot overflow (device status; a bug) */
 };
 
@@ -72,11 +79,12 @@ size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt);
 
 /*
  * The k lowest states of one QUBO (Algorithm 1 generalised from k = 1).
- *   Q         device, n x n (ldq >= n), float32 (QUBO_F32) or int32 (QUBO_I32)
+ *   Q         device, n x n (ldq >= n), of the type dt: float32, int32,
+ *             float64 or int64
  *   n         1 .. 63
- *   k         1 .. 64 (int32), 1 .. 56 (float32)
- *   energies  device, k entries: double (QUBO_F32) or int64_t (QUBO_I32);
- *             slots beyond 2^n hold +inf / INT64_MAX
+ *   k         1 .. 64 (int32, int64), 1 .. 56 (float32, float64)
+ *   energies  device, k entries: double (QUBO_F32, QUBO_F64) or int64_t
+ *             (QUBO_I32, QUBO_I64); slots beyond 2^n hold +inf / INT64_MAX
  *   masks     device, k entries; slots beyond 2^n hold ~0
  *   status    device, 1 int32: QUBO_OK, QUBO_ERR_NONFINITE, QUBO_ERR_RANGE or
  *             QUBO_ERR_UNCERTAIN
@@ -126,8 +134,8 @@ int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k,
 
 /*
  * The k lowest (energy, mask) pairs of `count` result lists of k_in entries
- * each (device, [count][k_in], energies double for QUBO_F32 / int64_t for
- * QUBO_I32, masks uint64), as written by qubo_bf_solve_range for disjoint
+ * each (device, [count][k_in], energies double for QUBO_F32 / QUBO_F64, int64_t
+ * for QUBO_I32 / QUBO_I64, masks uint64), as written by qubo_bf_solve_range for disjoint
  * ranges of one instance; sentinel entries are skipped and missing outputs
  * hold the sentinels.  k: 1 .. 64.  One launch on hip_stream, no workspace.
  */

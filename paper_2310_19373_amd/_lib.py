@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libqubo_bf.so")
 
 QUBO_F32 = 0
 QUBO_I32 = 1
+QUBO_F64 = 2
+QUBO_I64 = 3
 
 QUBO_OK = 0
 QUBO_ERR_INVALID_ARG = -1

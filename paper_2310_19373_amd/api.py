@@ -29,7 +29,7 @@ _STATUS = {
     _lib.QUBO_ERR_INVALID_ARG: "invalid instance size",
     _lib.QUBO_ERR_NONFINITE: "Q holds inf or NaN",
     _lib.QUBO_ERR_UNCERTAIN: "float certificate failed",
-    _lib.QUBO_ERR_RANGE: "int32 Q with sum |Q_ij| > 2^28",
+    _lib.QUBO_ERR_RANGE: "integer Q with sum |Q_ij| beyond the walk's exact range (2^28 int32, 2^50 int64)",
     _lib.QUBO_ERR_OVERFLOW: "internal candidate slot overflow",
 }
 
@@ -45,12 +45,19 @@ def _as_device(x, dtype=None, device=None):
     return x.to(dev).contiguous()
 
 
-def _qdtype(t: torch.Tensor) -> int:
-    if t.dtype == torch.float32:
-        return _lib.QUBO_F32
-    if t.dtype == torch.int32:
-        return _lib.QUBO_I32
-    raise TypeError("Q must be float32 or int32")
+_DTYPES = {torch.float32: _lib.QUBO_F32, torch.int32: _lib.QUBO_I32, torch.float64: _lib.QUBO_F64,
+           torch.int64: _lib.QUBO_I64}
+
+
+def _qdtype(t) -> int:
+    dt = _DTYPES.get(t.dtype if isinstance(t, torch.Tensor) else t)
+    if dt is None:
+        raise TypeError("Q must be float32, int32, float64 or int64")
+    return dt
+
+
+def _energy_dtype(dt: int):
+    return torch.float64 if dt in (_lib.QUBO_F32, _lib.QUBO_F64) else torch.int64
 
 
 def _stream(device) -> int:
@@ -76,10 +83,12 @@ def _check_upper(Q: torch.Tensor):
 def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = True):
     """The k lowest states of f_Q(x) = x^T Q x over x in {0,1}^n.
 
-    Q: (n, n) float32 or int32 tensor/array, upper triangular.
+    Q: (n, n) float32, int32, float64 or int64 tensor/array, upper triangular.
     Returns (energies, masks) on Q's GPU: float64 (float Q) or int64 (int Q),
     and int64 tensors holding the uint64 masks (bit i = x_i), ascending by
     (energy, mask).  Slots beyond 2^n hold +inf / INT64_MAX and mask -1.
+    int32 Q whose sum |Q_ij| exceeds the int32 walk's 2^28 is solved again as
+    int64 (the exact float64 walk).
     """
     Qd = _as_device(Q)
     if Qd.ndim != 2 or Qd.shape[0] != Qd.shape[1]:
@@ -95,7 +104,7 @@ def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = Tr
     dev = Qd.device
     with torch.cuda.device(dev):
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-        en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=dev)
+        en = torch.empty(k, dtype=_energy_dtype(dt), device=dev)
         masks = torch.empty(k, dtype=torch.int64, device=dev)
         status = torch.empty(1, dtype=torch.int32, device=dev)
         _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, n, dt, k, en.data_ptr(), masks.data_ptr(), status.data_ptr(),
@@ -103,7 +112,7 @@ def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = Tr
         try:
             _raise_status(status)
         except UncertainError:
-            if not retry_uncertain or dt != _lib.QUBO_F32:
+            if not retry_uncertain or dt not in (_lib.QUBO_F32, _lib.QUBO_F64):
                 raise
             old = _lib.get_tuning(_lib.TUNE_KPRIME)
             _lib.set_tuning(_lib.TUNE_KPRIME, 64)
@@ -111,6 +120,10 @@ def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = Tr
                 return solve(Qd, k, check_lower=False, retry_uncertain=False)
             finally:
                 _lib.set_tuning(_lib.TUNE_KPRIME, old)
+        except QuboError as e:
+            if e.code != _lib.QUBO_ERR_RANGE or dt != _lib.QUBO_I32:
+                raise
+            return solve(Qd.to(torch.int64), k, check_lower=False)
     return en, masks
 
 
@@ -134,7 +147,7 @@ def solve_range(Q, k: int, p_bits: int, p_begin: int, p_end: int, *, check_lower
     dev = Qd.device
     with torch.cuda.device(dev):
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-        en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=dev)
+        en = torch.empty(k, dtype=_energy_dtype(dt), device=dev)
         masks = torch.empty(k, dtype=torch.int64, device=dev)
         status = torch.empty(1, dtype=torch.int32, device=dev)
         _lib.check(L.qubo_bf_solve_range(Qd.data_ptr(), n, n, dt, k, p_bits, p_begin, p_end, en.data_ptr(),
@@ -171,7 +184,7 @@ class BatchedSolver:
     def __init__(self, batch: int, nmax: int, k: int = 1, dtype=torch.float32, device=None, graph: bool = False):
         self.batch, self.nmax, self.k = batch, nmax, k
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        self.dt = _lib.QUBO_F32 if dtype == torch.float32 else _lib.QUBO_I32
+        self.dt = _qdtype(dtype)
         L = _lib.lib()
         self.ws_bytes = L.qubo_bf_batched_workspace_size(batch, nmax, k, self.dt)
         if self.ws_bytes == 0:
@@ -180,8 +193,7 @@ class BatchedSolver:
         self.Q = torch.zeros((batch, nmax, nmax), dtype=dtype, device=d)
         self.ns = torch.zeros(batch, dtype=torch.int32, device=d)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=d)
-        self.energies = torch.empty((batch, k), dtype=torch.float64 if self.dt == _lib.QUBO_F32 else torch.int64,
-                                    device=d)
+        self.energies = torch.empty((batch, k), dtype=_energy_dtype(self.dt), device=d)
         self.masks = torch.empty((batch, k), dtype=torch.int64, device=d)
         self.status = torch.empty(batch, dtype=torch.int32, device=d)
         self.use_graph = graph
@@ -224,7 +236,7 @@ class BatchedSolver:
 def solve_batched(Qpad, ns, k: int = 1, *, check_lower: bool = True):
     """Independent k-lowest solves of many QUBOs.
 
-    Qpad: (batch, nmax, nmax) float32/int32, instance b in Qpad[b, :ns[b], :ns[b]].
+    Qpad: (batch, nmax, nmax) float32/int32/float64/int64, instance b in Qpad[b, :ns[b], :ns[b]].
     Returns (energies [batch, k], masks [batch, k]) on the GPU.
     """
     Qd = _as_device(Qpad)

@@ -78,8 +78,10 @@ Tuning& tuning() {
 
 int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-int kprime_for(int k, bool is_int) {
-  if (is_int) return k;
+// Candidate list length: k for the exact paths (int32, int64), else at least
+// 2k and k + 8 so that the certificate has room above the k-th value.
+int kprime_for(int k, bool exact) {
+  if (exact) return k;
   const int o = tuning().kprime;
   if (o > 0) return clampi(o, 1, kMaxKPrime);
   int kp = 2 * k > k + 8 ? 2 * k : k + 8;
@@ -182,7 +184,7 @@ Layout make_layout(int batch, int nmax, const PlanParams& pp, int64_t part_per_u
   L.ei = o;
   o += al(8 * (size_t)batch * 64);
   L.tab = o;
-  o += al(4 * (size_t)batch * steps * width);
+  o += al((size_t)(pp.tab_elem > 0 ? pp.tab_elem : 4) * batch * steps * width);
   L.rec = o;
   o += al(sizeof(StepRec) * (size_t)batch * steps);
   L.eod = o;
@@ -295,18 +297,30 @@ constexpr int64_t kSamplePart = 66;
 
 int logz_npairs(int nmax) { return nmax * (nmax + 1) / 2; }
 
-bool valid_dtype(qubo_dtype dt) { return dt == QUBO_F32 || dt == QUBO_I32; }
+bool valid_dtype(qubo_dtype dt) { return dt == QUBO_F32 || dt == QUBO_I32 || dt == QUBO_F64 || dt == QUBO_I64; }
 
-int check_k(int k, bool is_int) {
+int check_k(int k, bool exact) {
   if (k < 1 || k > kMaxKPrime) return fail(QUBO_ERR_INVALID_ARG, "k=%d outside [1, %d]", k, kMaxKPrime);
-  if (!is_int && k > kMaxKPrime - 8)
-    return fail(QUBO_ERR_INVALID_ARG, "k=%d outside [1, %d] for float32 Q", k, kMaxKPrime - 8);
+  if (!exact && k > kMaxKPrime - 8)
+    return fail(QUBO_ERR_INVALID_ARG, "k=%d outside [1, %d] for float Q", k, kMaxKPrime - 8);
   return QUBO_OK;
+}
+
+// The float64 walk (float64 and int64 Q) takes five inner bits and 8-byte
+// table entries.
+PlanParams with_dt(PlanParams pp, qubo_dtype dt) {
+  if (dt_wide(dt)) {
+    pp.inner = kInnerWide;
+    pp.tab_elem = 8;
+  } else {
+    pp.tab_elem = 4;
+  }
+  return pp;
 }
 
 // Enqueue plan -> prep -> tables -> walk -> finalize for a top-k call.
 int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const int32_t* ns, int n_single,
-             bool is_int, int k, PlanParams pp, int64_t units_hint, int64_t steps_hint, void* energies,
+             int dt, int k, PlanParams pp, int64_t units_hint, int64_t steps_hint, void* energies,
              uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
   int waves = grid_waves();
   if (units_hint > 0 && units_hint < waves) {
@@ -315,17 +329,17 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   }
   pp.waves = waves;
   HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
-  HIPCHK(launch_prep_inst(v, Q, ldq, stride, is_int, kInner, s));
-  HIPCHK(launch_prep_lanes(v, is_int, s));
+  HIPCHK(launch_prep_inst(v, Q, ldq, stride, dt, pp.inner, s));
+  HIPCHK(launch_prep_lanes(v, dt, s));
   // single small instances: the walk is shorter than the seed's latency.  A
   // prefix-range solve seeds inside its range (the planner's seed_fix).
-  if (ns != nullptr || n_single > 22) HIPCHK(launch_seed(v, is_int, s));
-  HIPCHK(launch_prep_tables(v, is_int, kInner, steps_hint, s));
+  if (ns != nullptr || n_single > 22) HIPCHK(launch_seed(v, dt, s));
+  HIPCHK(launch_prep_tables(v, dt, pp.inner, steps_hint, s));
   {
     ProfScope ps("walk_topk", s);
-    HIPCHK(launch_walk_topk(v, is_int, waves, s));
+    HIPCHK(launch_walk_topk(v, dt, waves, s));
   }
-  HIPCHK(launch_finalize_topk(v, Q, ldq, stride, is_int, k, energies, masks, status, fin_waves, s));
+  HIPCHK(launch_finalize_topk(v, Q, ldq, stride, dt, k, energies, masks, status, fin_waves, s));
   return QUBO_OK;
 }
 
@@ -406,9 +420,9 @@ int qubo_prof_collect(const char* name, double* total_ms, int64_t* launches) {
 
 size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt) {
   if (n < 1 || n > 63 || !valid_dtype(dt)) return 0;
-  const bool is_int = dt == QUBO_I32;
-  if (check_k(k, is_int) != QUBO_OK) return 0;
-  return make_layout(1, n, single_params(kprime_for(k, is_int), n), 0, 0).total;
+  const bool exact = dt_exact(dt);
+  if (check_k(k, exact) != QUBO_OK) return 0;
+  return make_layout(1, n, with_dt(single_params(kprime_for(k, exact), n), dt), 0, 0).total;
 }
 
 int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
@@ -417,16 +431,16 @@ int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void*
   if (n < 1 || n > 63) return fail(QUBO_ERR_INVALID_ARG, "n=%d outside [1, 63]", n);
   if (ldq < n) return fail(QUBO_ERR_INVALID_ARG, "ldq=%lld < n=%d", (long long)ldq, n);
   if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
-  const bool is_int = dt == QUBO_I32;
-  if (int rc = check_k(k, is_int)) return rc;
-  const int kp = kprime_for(k, is_int);
-  const PlanParams pp = single_params(kp, n);
+  const bool exact = dt_exact(dt);
+  if (int rc = check_k(k, exact)) return rc;
+  const int kp = kprime_for(k, exact);
+  const PlanParams pp = with_dt(single_params(kp, n), dt);
   const Layout L = make_layout(1, n, pp, 0, 0);
   if (ws_bytes < L.total)
     return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
   const Views v = make_views(ws, L, 1, n);
   const SplitH sh = split_host(n, pp);
-  return run_topk(v, Q, ldq, 0, nullptr, n, is_int, k, pp, int64_t(1) << sh.tb, int64_t(1) << sh.no, energies,
+  return run_topk(v, Q, ldq, 0, nullptr, n, dt, k, pp, int64_t(1) << sh.tb, int64_t(1) << sh.no, energies,
                   masks, status, 16, (hipStream_t)hip_stream);
 }
 
@@ -449,9 +463,9 @@ static PlanParams range_params(int kp, int n, int p_bits, int64_t p_begin, int64
 
 size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits) {
   if (n < 1 || n > 63 || !valid_dtype(dt) || p_bits < 1 || p_bits > 20 || p_bits > n - 12) return 0;
-  const bool is_int = dt == QUBO_I32;
-  if (check_k(k, is_int) != QUBO_OK) return 0;
-  return make_layout(1, n, range_params(kprime_for(k, is_int), n, p_bits, 0, 1), 0, 0).total;
+  const bool exact = dt_exact(dt);
+  if (check_k(k, exact) != QUBO_OK) return 0;
+  return make_layout(1, n, with_dt(range_params(kprime_for(k, exact), n, p_bits, 0, 1), dt), 0, 0).total;
 }
 
 int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int p_bits, int64_t p_begin,
@@ -461,17 +475,17 @@ int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k,
   if (n < 1 || n > 63) return fail(QUBO_ERR_INVALID_ARG, "n=%d outside [1, 63]", n);
   if (ldq < n) return fail(QUBO_ERR_INVALID_ARG, "ldq=%lld < n=%d", (long long)ldq, n);
   if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
-  const bool is_int = dt == QUBO_I32;
-  if (check_k(k, is_int) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
+  const bool exact = dt_exact(dt);
+  if (check_k(k, exact) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
   if (check_range(n, p_bits, p_begin, p_end) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
-  const int kp = kprime_for(k, is_int);
-  const PlanParams pp = range_params(kp, n, p_bits, p_begin, p_end);
+  const int kp = kprime_for(k, exact);
+  const PlanParams pp = with_dt(range_params(kp, n, p_bits, p_begin, p_end), dt);
   const Layout L = make_layout(1, n, pp, 0, 0);
   if (ws_bytes < L.total) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
   const Views v = make_views(ws, L, 1, n);
   const SplitH sh = split_host(n, pp);
   const int64_t units = (p_end - p_begin) << (sh.tb - p_bits);
-  return run_topk(v, Q, ldq, 0, nullptr, n, is_int, k, pp, units, int64_t(1) << sh.no, energies, masks, status,
+  return run_topk(v, Q, ldq, 0, nullptr, n, dt, k, pp, units, int64_t(1) << sh.no, energies, masks, status,
                   16, (hipStream_t)hip_stream);
 }
 
@@ -482,16 +496,16 @@ int qubo_bf_merge_topk(int count, int k_in, const void* energies_in, const uint6
     return fail(QUBO_ERR_INVALID_ARG, "count=%d, k_in=%d, k=%d: need count, k_in >= 1 and k in [1, %d]", count,
                 k_in, k, kMaxKPrime);
   if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
-  HIPCHK(launch_merge_topk(count, k_in, energies_in, masks_in, dt == QUBO_I32, k, energies, masks,
+  HIPCHK(launch_merge_topk(count, k_in, energies_in, masks_in, dt, k, energies, masks,
                            (hipStream_t)hip_stream));
   return QUBO_OK;
 }
 
 size_t qubo_bf_batched_workspace_size(int batch, int nmax, int k, qubo_dtype dt) {
   if (batch < 1 || nmax < 1 || nmax > 40 || !valid_dtype(dt)) return 0;
-  const bool is_int = dt == QUBO_I32;
-  if (check_k(k, is_int) != QUBO_OK) return 0;
-  return make_layout(batch, nmax, batched_params(kprime_for(k, is_int)), 0, 0).total;
+  const bool exact = dt_exact(dt);
+  if (check_k(k, exact) != QUBO_OK) return 0;
+  return make_layout(batch, nmax, with_dt(batched_params(kprime_for(k, exact)), dt), 0, 0).total;
 }
 
 int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns, qubo_dtype dt, int k,
@@ -501,17 +515,17 @@ int qubo_bf_solve_batched(int batch, const void* Q, int nmax, const int32_t* ns,
   if (batch < 1) return fail(QUBO_ERR_INVALID_ARG, "batch=%d < 1", batch);
   if (nmax < 1 || nmax > 40) return fail(QUBO_ERR_INVALID_ARG, "nmax=%d outside [1, 40]", nmax);
   if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
-  const bool is_int = dt == QUBO_I32;
-  if (int rc = check_k(k, is_int)) return rc;
-  const int kp = kprime_for(k, is_int);
-  const PlanParams pp = batched_params(kp);
+  const bool exact = dt_exact(dt);
+  if (int rc = check_k(k, exact)) return rc;
+  const int kp = kprime_for(k, exact);
+  const PlanParams pp = with_dt(batched_params(kp), dt);
   const Layout L = make_layout(batch, nmax, pp, 0, 0);
   if (ws_bytes < L.total)
     return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
   const Views v = make_views(ws, L, batch, nmax);
   const SplitH sh = split_host(nmax, pp);
   const int64_t steps_bound = (int64_t)batch << sh.no;
-  return run_topk(v, Q, nmax, (int64_t)nmax * nmax, ns, 0, is_int, k, pp, 0, steps_bound, energies, masks,
+  return run_topk(v, Q, nmax, (int64_t)nmax * nmax, ns, 0, dt, k, pp, 0, steps_bound, energies, masks,
                   status, 1, (hipStream_t)hip_stream);
 }
 
@@ -538,9 +552,9 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   const SplitH sh = split_host(nmax, pp);
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
-  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
-  HIPCHK(launch_prep_lanes(v, false, s));
-  HIPCHK(launch_prep_tables(v, false, kInner, steps_bound, s));
+  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, kDtF32, kInner, s));
+  HIPCHK(launch_prep_lanes(v, kDtF32, s));
+  HIPCHK(launch_prep_tables(v, kDtF32, kInner, steps_bound, s));
   HIPCHK(launch_prep_exp_tables(v, beta, kInner, steps_bound, s));
   {
     ProfScope ps("walk_exp", s);
@@ -569,9 +583,9 @@ static int run_moment_walk(int batch, const float* Q, int nmax, const int32_t* n
   const SplitH sh = split_host(nmax, pp);
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
-  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, pp.inner, s));
-  HIPCHK(launch_prep_lanes(v, false, s));
-  HIPCHK(launch_prep_tables(v, false, pp.inner, steps_bound, s));
+  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, kDtF32, pp.inner, s));
+  HIPCHK(launch_prep_lanes(v, kDtF32, s));
+  HIPCHK(launch_prep_tables(v, kDtF32, pp.inner, steps_bound, s));
   HIPCHK(launch_prep_exp_tables(v, beta, pp.inner, steps_bound, s));
   {
     ProfScope ps("walk_grad", s);
@@ -626,9 +640,9 @@ int qubo_logz_sample(int batch, const float* Q, int nmax, const int32_t* ns, con
   pp.waves = waves;
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
-  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, false, kInner, s));
-  HIPCHK(launch_prep_lanes(v, false, s));
-  HIPCHK(launch_prep_tables(v, false, kInner, steps_bound, s));
+  HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, kDtF32, kInner, s));
+  HIPCHK(launch_prep_lanes(v, kDtF32, s));
+  HIPCHK(launch_prep_tables(v, kDtF32, kInner, steps_bound, s));
   HIPCHK(launch_prep_exp_tables(v, beta, kInner, steps_bound, s));
   HIPCHK(launch_walk_exp(v, beta, waves, s));
   HIPCHK(launch_finalize_logz(v, beta, logz, status, s));

@@ -42,6 +42,21 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxKPrime = 64;             // candidate list length (one entry per lane)
 constexpr int32_t kIntInvalid = 1 << 30;   // table sentinel of the int32 path
 constexpr int64_t kIntSumLimit = int64_t(1) << 28;  // int32 path: sum |Q| bound
+// float64 walk: with sum |Q| <= 2^50 every intermediate of integer data (table
+// values, the running threshold offset, replay keys: at most 5 sum |Q| in
+// magnitude) is an integer below 2^53, so the walk is exact
+constexpr double kWideSumLimit = 1125899906842624.0;  // 2^50
+
+// input types (mirrors qubo_dtype of include/qubo_bf.h).  F32 walks in float32
+// and rescores in float64; I32 walks in int32; F64 and I64 walk in float64
+// (five inner bits: 32 table entries per lane), I64 exactly for sum |Q| <= 2^50.
+constexpr int kDtF32 = 0;
+constexpr int kDtI32 = 1;
+constexpr int kDtF64 = 2;
+constexpr int kDtI64 = 3;
+__host__ __device__ inline bool dt_exact(int dt) { return dt == kDtI32 || dt == kDtI64; }
+__host__ __device__ inline bool dt_wide(int dt) { return dt == kDtF64 || dt == kDtI64; }
+constexpr int kInnerWide = 5;               // inner bits of the float64 walk
 
 // status codes (mirrors include/qubo_bf.h)
 constexpr int32_t kOk = 0;

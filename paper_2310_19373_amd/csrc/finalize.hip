@@ -56,6 +56,39 @@ struct Rescore<int32_t> {
   }
 };
 
+template <>
+struct Rescore<double> {
+  using En = double;
+  __device__ static En sentinel() { return __builtin_inf(); }
+  __device__ static En energy(const double* Q, int ldq, int n, uint64_t m) {
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (!((m >> i) & 1)) continue;
+      double row = Q[i * ldq + i];
+      for (int j = i + 1; j < n; ++j)
+        if ((m >> j) & 1) row = __dadd_rn(row, Q[i * ldq + j]);
+      tot = __dadd_rn(tot, row);
+    }
+    return tot;
+  }
+};
+template <>
+struct Rescore<int64_t> {
+  using En = int64_t;
+  __device__ static En sentinel() { return INT64_MAX; }
+  __device__ static En energy(const int64_t* Q, int ldq, int n, uint64_t m) {
+    int64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!((m >> i) & 1)) continue;
+      int64_t row = Q[i * ldq + i];
+      for (int j = i + 1; j < n; ++j)
+        if ((m >> j) & 1) row += Q[i * ldq + j];
+      tot += row;
+    }
+    return tot;
+  }
+};
+
 __device__ __forceinline__ int64_t readlane_en(int64_t v, int l) { return readlane_i64(v, l); }
 __device__ __forceinline__ double readlane_en(double v, int l) { return readlane_f64(v, l); }
 
@@ -128,7 +161,7 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
     en = Rescore<Qin>::energy(sq, I->n, I->n, m);
   }
   wave_sort(en, m, lane);
-  if constexpr (std::is_same_v<Qin, float>) {
+  if constexpr (std::is_floating_point_v<Qin>) {
     const double thr_m = readlane_f64(lkey, kp - 1);
     const double ek = readlane_en(en, k - 1);
     if (st == 0 && I->eps > 0.0 && thr_m < __builtin_inf() && !(thr_m - I->eps > ek)) st = kErrUncertain;
@@ -145,7 +178,7 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
 // over disjoint prefix ranges of one instance -- into the k best by (energy,
 // mask).  One wave: entries stream through 64 at a time, and those that beat
 // the current k-th are inserted into the wave's sorted list.  Energies pass
-// through float64 keys, exact for the int path's |E| <= 2^28 as well.
+// through float64 keys, exact for the int paths' |E| <= 2^50 as well.
 template <class En>
 __global__ void __launch_bounds__(64) merge_topk_kernel(int count, int k_in, const En* ein, const uint64_t* min_,
                                                         int k, En* eout, uint64_t* mout) {
@@ -159,7 +192,7 @@ __global__ void __launch_bounds__(64) merge_topk_kernel(int count, int k_in, con
     uint64_t m = ~0ull;
     if (e < total) {
       const En x = ein[e];
-      if (x != Rescore<std::conditional_t<std::is_same_v<En, double>, float, int32_t>>::sentinel()) {
+      if (x != Rescore<En>::sentinel()) {
         key = (double)x;
         m = min_[e];
       }
@@ -175,23 +208,35 @@ __global__ void __launch_bounds__(64) merge_topk_kernel(int count, int k_in, con
   }
   if (lane < k) {
     const bool fin = lkey < __builtin_inf();
-    eout[lane] = fin ? (En)lkey : Rescore<std::conditional_t<std::is_same_v<En, double>, float, int32_t>>::sentinel();
+    eout[lane] = fin ? (En)lkey : Rescore<En>::sentinel();
     mout[lane] = fin ? lmask : ~0ull;
   }
 }
 
 }  // namespace
 
-hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t stride, bool is_int, int k,
+hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t stride, int dt, int k,
                                 void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,
                                 hipStream_t s) {
   const int w = max(1, min(kMaxFinWaves, waves_per_inst));
-  if (is_int)
-    hipLaunchKernelGGL(finalize_topk_kernel<int32_t>, dim3(v.batch), dim3(64 * w), 0, s, v, (const int32_t*)q, ldq,
-                       stride, k, (int64_t*)energies, masks, status);
-  else
-    hipLaunchKernelGGL(finalize_topk_kernel<float>, dim3(v.batch), dim3(64 * w), 0, s, v, (const float*)q, ldq,
-                       stride, k, (double*)energies, masks, status);
+  const dim3 g(v.batch), blk(64 * w);
+  switch (dt) {
+    case kDtI32:
+      hipLaunchKernelGGL(finalize_topk_kernel<int32_t>, g, blk, 0, s, v, (const int32_t*)q, ldq, stride, k,
+                         (int64_t*)energies, masks, status);
+      break;
+    case kDtF64:
+      hipLaunchKernelGGL(finalize_topk_kernel<double>, g, blk, 0, s, v, (const double*)q, ldq, stride, k,
+                         (double*)energies, masks, status);
+      break;
+    case kDtI64:
+      hipLaunchKernelGGL(finalize_topk_kernel<int64_t>, g, blk, 0, s, v, (const int64_t*)q, ldq, stride, k,
+                         (int64_t*)energies, masks, status);
+      break;
+    default:
+      hipLaunchKernelGGL(finalize_topk_kernel<float>, g, blk, 0, s, v, (const float*)q, ldq, stride, k,
+                         (double*)energies, masks, status);
+  }
   return hipGetLastError();
 }
 
@@ -199,9 +244,9 @@ hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int6
 
 namespace qbf {
 
-hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, bool is_int, int k, void* eout,
+hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, int dt, int k, void* eout,
                              uint64_t* mout, hipStream_t s) {
-  if (is_int)
+  if (dt_exact(dt))
     hipLaunchKernelGGL(merge_topk_kernel<int64_t>, dim3(1), dim3(64), 0, s, count, k_in, (const int64_t*)ein, min, k,
                        (int64_t*)eout, mout);
   else

@@ -14,9 +14,9 @@ struct Views {
   Inst* inst;
   uint64_t* gthr;
   uint32_t* flushcnt;
-  void* qs;        // [batch][nmax][nmax] double (float path) or int64 (int path)
+  void* qs;        // [batch][nmax][nmax] double (float walks) or int64 (int32 walk)
   void* ei;        // [batch][64] double or int64
-  void* tab;       // [total_steps][2^inner] float or int32, row-broadcast layout
+  void* tab;       // [total_steps][2^inner] float, int32 or double, row-broadcast layout
   StepRec* rec;    // [total_steps]
   double* eod;     // [total_steps] E_O(g(t)), dense (float path)
   int32_t* eoi;    // [total_steps] -E_O(g(t)), dense (int path)
@@ -47,6 +47,7 @@ struct PlanParams {
   // lie in [range_begin, range_end); range_bits = 0: every mask
   int range_bits;
   int64_t range_begin, range_end;
+  int tab_elem;  // bytes per step-table entry (0: 4)
 };
 
 // plan: bit split, unit/table/slot offsets, counters.  ns == nullptr: one
@@ -54,25 +55,26 @@ struct PlanParams {
 hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta,
                        const PlanParams& pp, hipStream_t s);
 // prep: symmetric Q, sums, E_I table, float/int validation.
-hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
+// dt: one of kDt* (the log-partition paths pass kDtF32).
+hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, int dt,
                             int inner, hipStream_t s);
 // per-instance lane table: contributions of the lane bits to E_P and to the
 // inner / outer cross fields, for each of the 64 lane values.
-hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s);
+hipError_t launch_prep_lanes(const Views& v, int dt, hipStream_t s);
 // a-priori threshold per instance from a greedy descent (after prep_inst).
-hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s);
+hipError_t launch_seed(const Views& v, int dt, hipStream_t s);
 // per-step tables of the outer walk; steps_bound >= total steps of the plan
 // (sizes the grid only: the kernel reads the exact count from the header).
-hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int64_t steps_bound, hipStream_t s);
+hipError_t launch_prep_tables(const Views& v, int dt, int inner, int64_t steps_bound, hipStream_t s);
 // persistent top-k walk.
-hipError_t launch_walk_topk(const Views& v, bool is_int, int waves, hipStream_t s);
+hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s);
 // merge candidate lists, rescore in float64 / int64, certificate, outputs.
-hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, bool is_int,
+hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, int dt,
                                 int k, void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,
                                 hipStream_t s);
 
 // merge of top-k lists from disjoint prefix ranges of one instance (one wave).
-hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, bool is_int, int k, void* eout,
+hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, int dt, int k, void* eout,
                              uint64_t* mout, hipStream_t s);
 // log-partition: factor tables (after prep_tables), forward walk, finalize.
 hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,

@@ -136,7 +136,9 @@ __device__ double absd(T x) {
   return fabs((double)x);
 }
 
-template <class Qin, class W>
+// Qin: input element type; W: exact accumulation type of the tables; E: the
+// walk's element type (float32 / int32 / float64), which sets the error bound.
+template <class Qin, class W, class E>
 __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, int64_t ldq, int64_t stride,
                                                         int inner) {
   __shared__ double red_a[256], red_r[256];
@@ -153,9 +155,9 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx / n, j = idx % n;
     const Qin val = (i <= j) ? Q[(int64_t)i * ldq + j] : Q[(int64_t)j * ldq + i];
-    if constexpr (std::is_same_v<Qin, float>) {
+    if constexpr (std::is_floating_point_v<Qin>) {
       if (!isfinite(val)) bad = 1;
-      if (i <= j && val != truncf(val)) frac = 1;
+      if (i <= j && (double)val != trunc((double)val)) frac = 1;
     }
     qs[(int64_t)i * nmax + j] = (W)(sgn * (double)val);
     if (i <= j) sabs += absd(val);
@@ -190,20 +192,36 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
   if (tid == 0) {
     const double sa = red_a[0];
     I->sumabs = sa;
-    if constexpr (std::is_same_v<W, double>) {
+    if constexpr (std::is_same_v<E, int32_t>) {
+      I->big = sa + 1.0;
+      I->eps = 0.0;
+      if (sa > (double)kIntSumLimit) I->status = kErrRange;
+    } else if constexpr (std::is_integral_v<Qin>) {
+      // integer Q on the float64 walk: exact below kWideSumLimit
+      I->big = sa + 1.0;
+      I->eps = 0.0;
+      if (sa > kWideSumLimit) I->status = kErrRange;
+    } else if constexpr (std::is_same_v<E, double>) {
+      // float64 walk: C', T', the step constants and the running Dp are sums
+      // of at most n + 2^14 + n^2 roundings of magnitude <= u sum|Q|
+      // (u = 2^-53), well inside 2^-36 sum|Q|; exact for integer-valued Q
+      // with sum |Q| <= 2^50.
+      I->big = sa * (1.0 + 1e-9) + 1.0;
+      I->eps = 0x1p-36 * sa;
+      if (!red_frac[0] && sa <= kWideSumLimit) I->eps = 0.0;
+      if (red_bad[0]) I->status = kErrNonfinite;
+    } else {
       I->big = sa * (1.0 + 1e-6) + 1.0;
       // |f32 table value - exact| <= 2u * R_I with u = 2^-24 (C', T' and their sum
       // are partial sums of the inner rows); the rest is float64 rounding.
-      I->eps = 3.0 * 0x1p-24 * red_r[0] + 1e-12 * sa;
+      // The running offset Dp and the replay keys are float64 (the bound of
+      // the float64 walk below).
+      I->eps = 3.0 * 0x1p-24 * red_r[0] + 0x1p-36 * sa;
       // Integer-valued float Q with sum |Q| <= 2^24: every table value, sum and
       // key is an integer below 2^24 in magnitude, exact in float32 and float64,
       // so the walk is exact (eps = 0) and ties are resolved like the int path.
       if (!red_frac[0] && sa <= 16777216.0) I->eps = 0.0;
       if (red_bad[0]) I->status = kErrNonfinite;
-    } else {
-      I->big = sa + 1.0;
-      I->eps = 0.0;
-      if (sa > (double)kIntSumLimit) I->status = kErrRange;
     }
   }
 }
@@ -425,44 +443,58 @@ hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const fl
   return hipGetLastError();
 }
 
-hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t stride, bool is_int, int inner,
+hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t stride, int dt, int inner,
                             hipStream_t s) {
-  if (is_int)
-    hipLaunchKernelGGL((prep_inst_kernel<int32_t, int64_t>), dim3(v.batch), dim3(256), 0, s, v,
-                       (const int32_t*)q, ldq, stride, inner);
-  else
-    hipLaunchKernelGGL((prep_inst_kernel<float, double>), dim3(v.batch), dim3(256), 0, s, v, (const float*)q,
-                       ldq, stride, inner);
+  const dim3 g(v.batch), blk(256);
+  switch (dt) {
+    case kDtI32:
+      hipLaunchKernelGGL((prep_inst_kernel<int32_t, int64_t, int32_t>), g, blk, 0, s, v, (const int32_t*)q, ldq,
+                         stride, inner);
+      break;
+    case kDtF64:
+      hipLaunchKernelGGL((prep_inst_kernel<double, double, double>), g, blk, 0, s, v, (const double*)q, ldq,
+                         stride, inner);
+      break;
+    case kDtI64:
+      hipLaunchKernelGGL((prep_inst_kernel<int64_t, double, double>), g, blk, 0, s, v, (const int64_t*)q, ldq,
+                         stride, inner);
+      break;
+    default:
+      hipLaunchKernelGGL((prep_inst_kernel<float, double, float>), g, blk, 0, s, v, (const float*)q, ldq, stride,
+                         inner);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_prep_lanes(const Views& v, bool is_int, hipStream_t s) {
-  if (is_int)
+hipError_t launch_prep_lanes(const Views& v, int dt, hipStream_t s) {
+  if (dt == kDtI32)
     hipLaunchKernelGGL(prep_lanes_kernel<int64_t>, dim3(v.batch), dim3(64), 0, s, v);
   else
     hipLaunchKernelGGL(prep_lanes_kernel<double>, dim3(v.batch), dim3(64), 0, s, v);
   return hipGetLastError();
 }
 
-hipError_t launch_seed(const Views& v, bool is_int, hipStream_t s) {
+hipError_t launch_seed(const Views& v, int dt, hipStream_t s) {
   if (v.seed_sweeps <= 0) return hipSuccess;  // seeding switched off
-  // padded n x n plus the diagonal, 8-byte exact entries (both paths) and a float32 copy
+  // padded n x n plus the diagonal, 8-byte exact entries (every path) and a float32 copy
   const size_t np = (size_t)((v.nmax + 3) & ~3);
   const size_t lds = (sizeof(double) + sizeof(float)) * (np * np + np);
-  if (is_int)
+  if (dt == kDtI32)
     hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), lds, s, v);
   else
     hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(64), lds, s, v);
   return hipGetLastError();
 }
 
-hipError_t launch_prep_tables(const Views& v, bool is_int, int inner, int64_t steps_bound, hipStream_t s) {
+hipError_t launch_prep_tables(const Views& v, int dt, int inner, int64_t steps_bound, hipStream_t s) {
   // one block per (instance, chunk of 256 steps); steps_bound / batch bounds
   // the steps of one instance
   const int64_t per_inst = (steps_bound + v.batch - 1) / v.batch;
   const dim3 grid((unsigned)v.batch, (unsigned)((per_inst + 255) / 256 > 0 ? (per_inst + 255) / 256 : 1));
-  if (is_int)
+  if (dt == kDtI32)
     hipLaunchKernelGGL((prep_tables_kernel<int64_t, int32_t>), grid, dim3(256), 0, s, v, inner);
+  else if (dt_wide(dt))
+    hipLaunchKernelGGL((prep_tables_kernel<double, double>), grid, dim3(256), 0, s, v, inner);
   else
     hipLaunchKernelGGL((prep_tables_kernel<double, float>), grid, dim3(256), 0, s, v, inner);
   return hipGetLastError();

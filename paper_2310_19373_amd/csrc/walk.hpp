@@ -13,13 +13,17 @@ namespace qbf {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <class E>
 struct Ar;
+// W: exact accumulation type; V: one lane's 16-byte share of a 256-byte T'
+// row; NB: inner states per lane (the row holds NB entries of E).
 template <>
 struct Ar<float> {
   using W = double;
   using V = f32x4;
+  static constexpr int NB = 64;
   __device__ static float inv() { return __builtin_inff(); }
   __device__ static float mn(float a, float b) { return __builtin_fminf(a, b); }
 };
@@ -27,8 +31,17 @@ template <>
 struct Ar<int32_t> {
   using W = int64_t;
   using V = i32x4;
+  static constexpr int NB = 64;
   __device__ static int32_t inv() { return kIntInvalid; }
   __device__ static int32_t mn(int32_t a, int32_t b) { return a < b ? a : b; }
+};
+template <>
+struct Ar<double> {
+  using W = double;
+  using V = f64x2;
+  static constexpr int NB = 32;
+  __device__ static double inv() { return __builtin_inf(); }
+  __device__ static double mn(double a, double b) { return __builtin_fmin(a, b); }
 };
 
 // acc = min(acc, C'(16K+Q) + T'(16K+Q)) over Q = 0..15 for register K of the
@@ -39,6 +52,39 @@ __device__ __forceinline__ void block_min(E& acc, E t, const E* C) {
   const E e1 = row_bcast<Q + 1>(t) + C[16 * K + Q + 1];
   acc = Ar<E>::mn(Ar<E>::mn(acc, e0), e1);
   if constexpr (Q + 2 < 16) block_min<K, Q + 2>(acc, t, C);
+}
+
+// float64 walk: acc = min(acc, C'(16K+Q) + T'(16K+Q)) over Q = 0..15.  The
+// sixteen row broadcasts are 64-bit DPP moves (gfx950 has no DPP form of
+// v_add_f64), one asm block so that one s_nop covers the hazard of a VALU
+// write to t just before; then one v_add_f64 and one v_min_f64 per state.
+template <int K>
+__device__ __forceinline__ void block_min_f64(double& acc, double t, const double* C) {
+  double b[16];
+  asm("s_nop 1\n"
+      "v_mov_b64_dpp %0, %16 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %1, %16 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %2, %16 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %3, %16 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %4, %16 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %5, %16 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %6, %16 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %7, %16 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %8, %16 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %9, %16 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %10, %16 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %11, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %12, %16 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %13, %16 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %14, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+      "v_mov_b64_dpp %15, %16 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+      : "=&v"(b[0]), "=&v"(b[1]), "=&v"(b[2]), "=&v"(b[3]), "=&v"(b[4]), "=&v"(b[5]), "=&v"(b[6]),
+        "=&v"(b[7]), "=&v"(b[8]), "=&v"(b[9]), "=&v"(b[10]), "=&v"(b[11]), "=&v"(b[12]), "=&v"(b[13]),
+        "=&v"(b[14]), "=&v"(b[15])
+      : "v"(t));
+#pragma unroll
+  for (int q = 0; q < 16; q += 2)
+    acc = __builtin_fmin(__builtin_fmin(acc, b[q] + C[16 * K + q]), b[q + 1] + C[16 * K + q + 1]);
 }
 
 __device__ __forceinline__ int find_unit(const Views& v, uint64_t u) {

@@ -5,7 +5,8 @@
 // sub-walks whose results are min-combined).  Per lane and unit:
 //
 //   * lane init: E_P, the per-lane inner table C'(j) = E_I(j) + X_PI(p, j)
-//     (64 entries, float32 or int32, in VGPRs) and the per-lane cross fields
+//     (64 entries of float32 or int32, or 32 of float64, in VGPRs) and the
+//     per-lane cross fields
 //     c_l = sum_{v in prefix} S_{l v} x_v of the outer bits (LDS);
 //   * outer walk over t = 0 .. 2^no - 1 in reflected Gray order: step t flips
 //     bit l = CTZ(t) (Sec. 2.2), turning it on iff bit l+1 of t is 0; the
@@ -13,7 +14,9 @@
 //     E_O(g(t)) (the single-flip update of Eq. 2, Sec. 2.1, restricted to the prefix/outer cross terms);
 //   * 64 inner states per step: e_j = C'(j) + T'(g(t); j), with T' broadcast
 //     across each 16-lane row by DPP (one v_add_*_dpp per state) and folded by
-//     v_min3 (half an instruction per state);
+//     v_min3 (half an instruction per state); the float64 walk takes 32 inner
+//     states per step at three instructions per state (v_mov_b64_dpp,
+//     v_add_f64, v_min_f64);
 //   * if the block minimum can beat the wave's threshold (rare after warm-up),
 //     the block is replayed with exact float64 / int64 keys and the candidates
 //     are inserted into the wave's sorted top-K' list (lexicographic (energy,
@@ -108,31 +111,33 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
                                           uint64_t& lmask, uint64_t& pub, typename Ar<E>::W* myc, int lane) {
   using W = typename Ar<E>::W;
   using V = typename Ar<E>::V;
+  constexpr int NB = Ar<E>::NB;
+  constexpr bool kInt = std::is_same_v<E, int32_t>;
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
 
   // ---- lane init: prefix energy, inner table, outer cross fields
-  E C[kInnerStates];
-  const W EP = lane_init<E, kInnerStates>(v, b, I, local, valid, myc, lane, C);
+  E C[NB];
+  const W EP = lane_init<E, NB>(v, b, I, local, valid, myc, lane, C);
 
   // ---- outer walk
   // Dp = thr - E_P - X_PO(p, g(t)) is kept instead of the running value itself:
   // the filter of step t is  min_j e_j <= Dp - E_O(g(t)).  A threshold change by
   // delta moves Dp by delta.
-  using Acc = std::conditional_t<std::is_same_v<E, float>, double, int32_t>;
+  using Acc = std::conditional_t<kInt, int32_t, double>;
   // pub also tracks the lowest threshold seen, so a wave publishes (one
   // atomic) only a value below what the instance already has
   const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
   double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
-  Acc Dp = std::is_same_v<E, float> ? (Acc)(thr - (double)EP) : (Acc)((int32_t)thr - (int32_t)EP);
+  Acc Dp = kInt ? (Acc)((int32_t)thr - (int32_t)EP) : (Acc)(thr - (double)EP);
   const uint32_t steps = 1u << I.no;
   // T' rows through a buffer resource: per-lane byte offset in a VGPR (fixed),
   // per-step row offset in an SGPR, no address arithmetic on the VALU; reads
   // past the instance's rows return zeros.
   const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(gp((const E*)v.tab) + I.tab_off * kInnerStates), (short)0,
-      (int)(steps * (uint32_t)(kInnerStates * sizeof(E))), 0x00020000);
+      (void*)(gp((const E*)v.tab) + I.tab_off * NB), (short)0, (int)(steps * (uint32_t)(NB * sizeof(E))),
+      0x00020000);
   const int qoff = (lane & 15) * 16;
   const gptr<const double> eod = gp((const double*)v.eod) + I.tab_off;
   const gptr<const int32_t> eoi = gp((const int32_t*)v.eoi) + I.tab_off;
@@ -150,35 +155,37 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
     const uint32_t tt = t < steps ? t : steps - 1;
     Ops o;
     o.tv = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(
-                                     trs, qoff, (int)(tt * (uint32_t)(kInnerStates * sizeof(E))), 0));
-    if constexpr (std::is_same_v<E, float>) o.eo = eod[tt];
-    else o.eo = eoi[tt];
+                                     trs, qoff, (int)(tt * (uint32_t)(NB * sizeof(E))), 0));
+    if constexpr (kInt) o.eo = eoi[tt];
+    else o.eo = eod[tt];
     return o;
   };
   // Threshold refresh: fold an improvement of thr into Dp.
   auto retune = [&](double nthr) {
-    if constexpr (std::is_same_v<E, float>) {
-      Dp += nthr - thr;
-    } else {
-      Dp += (int32_t)nthr - (int32_t)thr;
-    }
+    if constexpr (kInt) Dp += (int32_t)nthr - (int32_t)thr;
+    else Dp += nthr - thr;
     thr = nthr;
   };
   // Block minimum over the 64 inner states of step t and the filter.
   auto body = [&](uint32_t t, const Ops& o) {
     E acc = Ar<E>::inv();
-    block_min<0, 0>(acc, o.tv.x, C);
-    block_min<1, 0>(acc, o.tv.y, C);
-    block_min<2, 0>(acc, o.tv.z, C);
-    block_min<3, 0>(acc, o.tv.w, C);
+    if constexpr (std::is_same_v<E, double>) {
+      block_min_f64<0>(acc, o.tv.x, C);
+      block_min_f64<1>(acc, o.tv.y, C);
+    } else {
+      block_min<0, 0>(acc, o.tv.x, C);
+      block_min<1, 0>(acc, o.tv.y, C);
+      block_min<2, 0>(acc, o.tv.z, C);
+      block_min<3, 0>(acc, o.tv.w, C);
+    }
     bool hit;
-    if constexpr (std::is_same_v<E, float>) hit = (double)acc <= Dp - o.eo;
-    else hit = acc <= Dp + o.eo;
+    if constexpr (kInt) hit = acc <= Dp + o.eo;
+    else hit = (double)acc <= Dp - o.eo;
     if (__builtin_expect(ballot(hit) != 0, 0)) {
       double nthr = thr;
       W KE;
-      if constexpr (std::is_same_v<E, float>) KE = thr - Dp + o.eo;
-      else KE = (int64_t)(int32_t)thr - (int64_t)Dp - (int64_t)o.eo;
+      if constexpr (kInt) KE = (int64_t)(int32_t)thr - (int64_t)Dp - (int64_t)o.eo;
+      else KE = thr - Dp + o.eo;
       replay<E>(v, b, I, t, p, valid, KE, nthr, lkey, lmask, pub, myc, lane);
       retune(nthr);
     }
@@ -187,11 +194,11 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   auto flip_on = [&](W c) { Dp -= (Acc)c; };
   auto flip_off = [&](W c) { Dp += (Acc)c; };
   auto flip_sign = [&](bool off, W c) {  // sign known only at run time (uniform)
-    if constexpr (std::is_same_v<E, float>) {
-      Dp = __builtin_fma(off ? 1.0 : -1.0, c, Dp);
-    } else {
+    if constexpr (kInt) {
       if (off) flip_off(c);
       else flip_on(c);
+    } else {
+      Dp = __builtin_fma(off ? 1.0 : -1.0, c, Dp);
     }
   };
   auto flip = [&](uint32_t t) {  // general flip: bit CTZ(t), off iff bit CTZ(t)+1 of t is set
@@ -253,7 +260,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
 }
 
 template <class E>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_kernel(Views v) {
+__device__ __forceinline__ void walk_topk_body(const Views& v) {
   using W = typename Ar<E>::W;
   __shared__ W ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
@@ -281,12 +288,24 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
   if (cur >= 0) flush(v, cur, lkey, lmask, lane);
 }
 
+// Three waves per SIMD for the float32 / int32 walks; two for the float64
+// walk (its 32-entry table and broadcast temporaries take 2x the VGPRs).
+template <class E>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_kernel(Views v) {
+  walk_topk_body<E>(v);
+}
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_topk_f64_kernel(Views v) {
+  walk_topk_body<double>(v);
+}
+
 }  // namespace
 
-hipError_t launch_walk_topk(const Views& v, bool is_int, int waves, hipStream_t s) {
+hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s) {
   const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (is_int)
+  if (dt == kDtI32)
     hipLaunchKernelGGL(walk_topk_kernel<int32_t>, dim3(blocks), dim3(kBlock), 0, s, v);
+  else if (dt_wide(dt))
+    hipLaunchKernelGGL(walk_topk_f64_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
   else
     hipLaunchKernelGGL(walk_topk_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, v);
   return hipGetLastError();

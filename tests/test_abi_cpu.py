@@ -49,6 +49,11 @@ def test_workspace_queries_validate():
     assert L.qubo_bf_workspace_size(40, 16, 0) > L.qubo_bf_workspace_size(20, 16, 0)
     assert L.qubo_bf_batched_workspace_size(4096, 28, 1, 0) > 0
     assert L.qubo_bf_batched_workspace_size(4096, 41, 1, 0) == 0
+    # float64 (2) and int64 (3) Q: the float64 walk; k limits as float / int
+    assert L.qubo_bf_workspace_size(40, 56, 2) > 0 and L.qubo_bf_workspace_size(40, 57, 2) == 0
+    assert L.qubo_bf_workspace_size(40, 64, 3) > 0
+    assert L.qubo_bf_batched_workspace_size(64, 30, 4, 2) > 0 and L.qubo_bf_batched_workspace_size(64, 30, 4, 3) > 0
+    assert L.qubo_bf_range_workspace_size(40, 16, 2, 4) > 0 and L.qubo_bf_workspace_size(20, 1, 4) == 0
 
 
 FAKE = 256  # a non-null dummy address: every case below is rejected before use
@@ -56,7 +61,7 @@ FAKE = 256  # a non-null dummy address: every case below is rejected before use
 
 @pytest.mark.parametrize("case,code", [
     (dict(Q=None), -1), (dict(n=0), -1), (dict(n=64), -1), (dict(ldq=5), -1),
-    (dict(dt=3), -1), (dict(k=0), -1), (dict(k=57), -1), (dict(status=None), -1),
+    (dict(dt=4), -1), (dict(k=0), -1), (dict(k=57), -1), (dict(dt=2, k=57), -1), (dict(status=None), -1),
     (dict(ws_bytes=16), -3),
 ])
 def test_solve_rejects_before_any_hip_call(case, code):

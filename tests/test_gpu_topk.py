@@ -159,11 +159,28 @@ def test_nonfinite_and_range_status(gpu_lib):
     with pytest.raises(api.QuboError) as ei:
         api.solve(Q, 1)
     assert ei.value.code == -2
+    # int32 Q beyond the int32 walk's 2^28: the ABI reports QUBO_ERR_RANGE in
+    # status; the Python layer then solves it as int64 (exact)
+    import torch
+
+    from paper_2310_19373_amd import _lib
+
     Qi = np.zeros((4, 4), dtype=np.int32)
     Qi[0, 0] = 2**29
-    with pytest.raises(api.QuboError) as ei:
-        api.solve(Qi, 1)
-    assert ei.value.code == -6
+    Qi[1, 1] = -3
+    Qd = torch.from_numpy(Qi).cuda()
+    L = _lib.lib()
+    wsb = L.qubo_bf_workspace_size(4, 1, _lib.QUBO_I32)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    en = torch.empty(1, dtype=torch.int64, device="cuda")
+    mk = torch.empty(1, dtype=torch.int64, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    _lib.check(L.qubo_bf_solve(Qd.data_ptr(), 4, 4, _lib.QUBO_I32, 1, en.data_ptr(), mk.data_ptr(), st.data_ptr(),
+                               ws.data_ptr(), wsb, None))
+    torch.cuda.synchronize()
+    assert int(st.item()) == -6
+    e, m = api.solve(Qi, 1)
+    assert int(e[0]) == -3 and int(m[0]) == 2
 
 
 def test_forced_small_candidate_list_is_uncertain(gpu_lib):

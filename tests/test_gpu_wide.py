@@ -1,0 +1,127 @@
+"""float64 and int64 Q on the float64 walk, against the oracle's float64 /
+int64 top-k over the same stored values.
+
+float64 Q: the k best masks must equal the oracle's and the energies are the
+same canonical float64 sums (compared bit for bit); int64 Q: exact.  The
+float64 walk on float32-valued Q must reproduce the float32 path exactly (the
+same numbers, the same canonical rescoring).  int32 Q whose sum exceeds the
+int32 walk's 2^28 is solved through int64 by the Python layer."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2310_19373_amd import _lib, api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _u64(xs):
+    return [int(x) & (2**64 - 1) for x in xs]
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _f64(n, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return np.triu(rng.standard_normal((n, n)) * scale + 1e-9 * rng.standard_normal((n, n)))
+
+
+@pytest.mark.parametrize("n,k", [(1, 2), (5, 40), (14, 8), (20, 16), (24, 1), (26, 20)])
+def test_f64_against_oracle(gpu_lib, n, k):
+    Q = _f64(n, 1000 + n, 1 / math.sqrt(n))
+    print(f"f64 n={n} k={k}", flush=True)
+    e, m = api.solve(Q, k)
+    E, M = oracle.topk(Q, k)
+    assert _u64(_np(m)) == _u64(M)
+    assert np.array_equal(_np(e), E)
+
+
+@pytest.mark.parametrize("n,k", [(3, 9), (12, 64), (22, 5), (25, 16)])
+def test_i64_exact_against_oracle(gpu_lib, n, k):
+    rng = np.random.default_rng(1100 + n)
+    Q = np.triu(rng.integers(-2**38, 2**38, (n, n), dtype=np.int64))
+    assert np.abs(Q).sum() <= 2**50
+    print(f"i64 n={n} k={k}", flush=True)
+    e, m = api.solve(Q, k)
+    E, M = oracle.topk(Q, k)
+    assert _u64(_np(m)) == _u64(M)
+    assert np.array_equal(_np(e), E)
+
+
+def test_i64_beyond_exact_range_is_reported(gpu_lib):
+    Q = np.zeros((6, 6), dtype=np.int64)
+    Q[0, 0] = 2**50
+    Q[1, 2] = 5
+    with pytest.raises(_lib.QuboError) as ei:
+        api.solve(Q, 1)
+    assert ei.value.code == _lib.QUBO_ERR_RANGE
+
+
+def test_int32_with_large_sum_goes_through_int64(gpu_lib):
+    n = 24
+    Q = inputs.random_i32(n, 1200, -2**24, 2**24)
+    assert np.abs(Q.astype(np.int64)).sum() > 2**28
+    e, m = api.solve(Q, 10)
+    E, M = oracle.topk(Q, 10)
+    assert _u64(_np(m)) == _u64(M)
+    assert np.array_equal(_np(e), E)
+
+
+def test_f64_walk_reproduces_f32_path_on_float32_values(gpu_lib):
+    # the n=40 planted workload: float32 values widened to float64
+    Q, xstar = inputs.single_n40_f32_planted()
+    e32, m32 = api.solve(Q, 16)
+    e64, m64 = api.solve(Q.astype(np.float64), 16)
+    assert torch.equal(m32, m64) and torch.equal(e32, e64)
+    assert int(m64[0]) == int(xstar)
+
+
+def test_f64_ties_zero_and_integer_valued(gpu_lib):
+    # zero Q: every state ties at 0, masks 0..k-1 (exact walk: eps = 0)
+    e, m = api.solve(np.zeros((20, 20)), 12)
+    assert _np(m).tolist() == list(range(12)) and np.all(_np(e) == 0)
+    # integer-valued float64 with heavy ties
+    rng = np.random.default_rng(1300)
+    Q = np.triu(rng.integers(-2, 3, (18, 18))).astype(np.float64)
+    e, m = api.solve(Q, 30)
+    E, M = oracle.topk(Q, 30)
+    assert _u64(_np(m)) == _u64(M) and np.array_equal(_np(e), E)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "i64"])
+def test_batched_wide_uneven(gpu_lib, dtype):
+    rng = np.random.default_rng(1400)
+    ns = rng.integers(1, 23, 48).astype(np.int32)
+    nmax = int(ns.max())
+    Q = np.zeros((48, nmax, nmax), dtype=np.float64 if dtype == "f64" else np.int64)
+    for b, n in enumerate(ns):
+        if dtype == "f64":
+            Q[b, :n, :n] = _f64(int(n), 1500 + b)
+        else:
+            Q[b, :n, :n] = np.triu(rng.integers(-2**33, 2**33, (n, n), dtype=np.int64))
+    print(f"batched {dtype}", flush=True)
+    e, m = api.solve_batched(Q, ns, 3)
+    e, m = _np(e), _np(m)
+    for b, n in enumerate(ns):
+        E, M = oracle.topk(Q[b, :n, :n], 3)
+        assert _u64(m[b]) == _u64(M), b
+        assert np.array_equal(e[b], E), b
+
+
+def test_f64_ranges_merge_to_full(gpu_lib):
+    n, k, pb = 26, 6, 3
+    Q = _f64(n, 1600, 0.5)
+    parts = []
+    for lo, hi in ((0, 3), (3, 4), (4, 8)):
+        e, m = api.solve_range(Q, k, pb, lo, hi)
+        E, M = oracle.topk(Q, k, lo=lo << (n - pb), hi=hi << (n - pb))
+        assert _u64(_np(m)) == _u64(M) and np.array_equal(_np(e), E)
+        parts.append((e, m))
+    me, mm = api.merge_topk(parts, k)
+    fe, fm = api.solve(Q, k)
+    assert torch.equal(me, fe) and torch.equal(mm, fm)
