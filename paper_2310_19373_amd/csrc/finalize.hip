@@ -143,13 +143,23 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   }
   __syncthreads();
   if (w != 0) return;
+  // the other waves' sorted lists: only entries before the current K'-th can
+  // enter, and once one fails the rest of that list fails too
   for (int o = 1; o < nw; ++o) {
     const double ok = sk[o][lane];
     const uint64_t om = sm[o][lane];
-    for (int i = 0; i < kp; ++i) {
-      const double ck = readlane_f64(ok, i);
-      if (!(ck < __builtin_inf())) break;
-      list_insert(lkey, lmask, ck, readlane_u64(om, i), kp, lane);
+    double tk = readlane_f64(lkey, kp - 1);
+    uint64_t tm = readlane_u64(lmask, kp - 1);
+    uint64_t bal = ballot(lane < kp && ok < __builtin_inf() && before(ok, om, tk, tm));
+    while (bal) {
+      const int src = __builtin_ctzll(bal);
+      bal &= bal - 1;
+      const double ck = readlane_f64(ok, src);
+      const uint64_t cm = readlane_u64(om, src);
+      if (!before(ck, cm, tk, tm)) break;
+      list_insert(lkey, lmask, ck, cm, kp, lane);
+      tk = readlane_f64(lkey, kp - 1);
+      tm = readlane_u64(lmask, kp - 1);
     }
   }
   int32_t st = st0;

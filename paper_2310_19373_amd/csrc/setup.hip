@@ -275,56 +275,92 @@ __device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
   return (a0 + a1) + (a2 + a3);
 }
 
-// A-priori threshold for instance b.  Each lane runs a greedy one-flip descent
-// from its own start (lane 0 from x = 0); the best local minimum x* and its n
-// one-flip neighbours are n + 1 distinct states, so the K'-th smallest of their
-// values bounds the instance's K'-th smallest value from above.  Published with
-// the float filter's error margin, the bound discards nothing the walk would
-// keep; it only spares each wave the replays of its cold start.  A prefix-range
-// solve keeps its top seed_fix bits at the range's first prefix and descends
-// over the free bits only, so that x* and its free-bit neighbours lie in the
-// range and bound the range's K'-th smallest value.
+// The same for a float32 row, 16-byte LDS loads (np is a multiple of 4 and
+// rows start 16-byte aligned) and 32-bit halves of x.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float field_f4(const float* row, int np, uint64_t x) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  for (int j = 0; j < np; j += 4) {
+    const f32x4_t r = *(const f32x4_t*)(row + j);
+    const uint32_t bits = j < 32 ? lo >> j : hi >> (j - 32);
+    a0 += (bits & 1u) ? r.x : 0.f;
+    a1 += (bits & 2u) ? r.y : 0.f;
+    a2 += (bits & 4u) ? r.z : 0.f;
+    a3 += (bits & 8u) ? r.w : 0.f;
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
+constexpr int kSeedThreads = 256;  // descents of a single instance (one per thread)
+
+// A-priori threshold for instance b.  Each thread (64 or 256) runs a greedy
+// one-flip descent from its own start (thread 0 from x = 0).  The best local
+// minimum x*, its n one-flip and n(n-1)/2 two-flip neighbours are distinct
+// states, so the K'-th smallest of their values bounds the instance's K'-th
+// smallest value from above.  Published with the float filter's error margin,
+// the bound discards nothing the walk would keep; it only spares each wave the
+// replays of its cold start.  A prefix-range solve keeps its top seed_fix bits
+// at the range's first prefix and descends over the free bits only, so that
+// x* and its free-bit neighbours lie in the range and bound the range's K'-th
+// smallest value.
 //
 // With S the symmetric off-diagonal part and d the diagonal,
 //   f(x) = sum_i x_i (d_i + h_i(x) / 2),  f(x ^ e_i) = f(x) + (1 - 2 x_i)(d_i + h_i(x)),
-// so lane i evaluates one field of x* and the wave sums: O(n) per lane.
+// so lane i evaluates one field of x* and the wave sums: O(n) per lane; a
+// two-flip value adds s_i s_j S_ij (s = 1 - 2x) to the two one-flip changes.
 template <class W>
-__global__ void __launch_bounds__(64) seed_kernel(Views v) {
-  extern __shared__ unsigned char seed_lds[];
-  const int b = blockIdx.x, lane = threadIdx.x;
+__global__ void __launch_bounds__(kSeedThreads) seed_kernel(Views v) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char seed_lds[];
+  __shared__ float best_f[kSeedThreads / kWave];
+  __shared__ uint64_t best_x[kSeedThreads / kWave];
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nt = blockDim.x, nwv = nt >> 6;
   const Inst* I = &v.inst[b];
-  if (I->status != 0) return;
+  if (I->status != 0) return;  // uniform over the block
   const int n = I->n, kp = I->kprime, nm = v.nmax;
   const int fix = I->seed_fix, nf = n - fix;  // free (searched) bits: [0, nf)
-  if (kp > nf + 1) return;
   const int np = (n + 3) & ~3;
-  // exact (W) and float32 copies of S with zero diagonal and padded rows, and d
+  // exact (W) and float32 copies of S with zero diagonal and padded rows, and
+  // d; the block's threads fill them with several independent loads each
   W* sw = (W*)seed_lds;
   W* dw = sw + np * np;
   float* sf = (float*)(dw + np);
   float* df = sf + np * np;
   const W* qg = (const W*)v.qs + (int64_t)b * nm * nm;
-  for (int e = lane; e < np * np; e += kWave) {
-    const int i = e / np, j = e % np;
-    const W q = (i < n && j < n && i != j) ? qg[(int64_t)i * nm + j] : (W)0;
-    sw[e] = q;
-    sf[e] = (float)q;
+  constexpr int kU = 4;
+  for (int e0 = tid; e0 < np * np; e0 += kU * nt) {
+    W q[kU];
+#pragma unroll
+    for (int d = 0; d < kU; ++d) {
+      const int e = e0 + d * nt;
+      const int i = e / np, j = e % np;
+      q[d] = (e < np * np && i < n && j < n && i != j) ? qg[(int64_t)i * nm + j] : (W)0;
+    }
+#pragma unroll
+    for (int d = 0; d < kU; ++d) {
+      const int e = e0 + d * nt;
+      if (e < np * np) {
+        sw[e] = q[d];
+        sf[e] = (float)q[d];
+      }
+    }
   }
-  for (int i = lane; i < np; i += kWave) {
+  for (int i = tid; i < np; i += nt) {
     dw[i] = i < n ? qg[(int64_t)i * nm + i] : (W)0;
     df[i] = (float)dw[i];
   }
   __syncthreads();
   const uint64_t free = nf >= 64 ? ~0ull : ((1ull << nf) - 1);
   const uint64_t base = fix > 0 ? ((uint64_t)I->local_off >> (I->tb - fix)) << nf : 0;
-  uint64_t x = base | (lane == 0 ? 0 : (mix64(((uint64_t)b << 6) | (uint64_t)lane) & free));
+  uint64_t x = base | (tid == 0 ? 0 : (mix64(((uint64_t)b << 8) | (uint64_t)tid) & free));
   // descent in float32 (any states back the bound, so neither convergence nor
   // exact deltas matter here): at most `sweeps` passes over the bits
   const int sweeps = v.seed_sweeps < 4 * n ? v.seed_sweeps : 4 * n;
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     bool moved = false;
     for (int i = 0; i < nf; ++i) {
-      const float g = df[i] + field(sf + i * np, np, x);
+      const float g = df[i] + field_f4(sf + i * np, np, x);
       if ((((x >> i) & 1) ? -g : g) < 0.f) {
         x ^= 1ull << i;
         moved = true;
@@ -332,14 +368,24 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
     }
     if (!moved) break;
   }
-  // best local minimum over the wave by its float32 value, ties to the lower lane
+  // best local minimum of each wave by its float32 value, ties to the lower
+  // lane, then the best of the waves, ties to the lower wave
   float fx = 0.f;
   for (int i = 0; i < n; ++i)
-    if ((x >> i) & 1) fx += df[i] + 0.5f * field(sf + i * np, np, x);
+    if ((x >> i) & 1) fx += df[i] + 0.5f * field_f4(sf + i * np, np, x);
   double key = (double)fx;
   uint64_t mask = x;
   wave_sort(key, mask, lane);
-  const uint64_t xs = readlane_u64(mask, 0);
+  if (lane == 0) {
+    best_f[w] = (float)key;
+    best_x[w] = mask;
+  }
+  __syncthreads();
+  if (w != 0) return;
+  int bw = 0;
+  for (int o = 1; o < nwv; ++o)
+    if (best_f[o] < best_f[bw]) bw = o;
+  const uint64_t xs = uniform_u64(best_x[bw]);
   // exact values: lane i < n evaluates field i of x*
   W gi = 0, term = 0;
   if (lane < n) {
@@ -351,17 +397,50 @@ __global__ void __launch_bounds__(64) seed_kernel(Views v) {
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
   if constexpr (std::is_same_v<W, double>) tot = uniform_f64(tot) * 0.5;
   else tot = (W)uniform_u64((uint64_t)tot) / 2;  // even: 2 sum_i x_i d_i + 2 sum_{i<j} S_ij x_i x_j
+  // x* and its one-flip neighbours (D_i = f(x* ^ e_i) - f(x*)), sorted: the
+  // first K' form the candidate list
+  const W si = ((xs >> lane) & 1) ? (W)-1 : (W)1;
+  const W Di = lane < nf ? si * gi : (W)0;
   key = __builtin_inf();
   mask = ~0ull;
   if (lane < nf) {
     mask = xs ^ (1ull << lane);
-    key = (double)(((xs >> lane) & 1) ? tot - gi : tot + gi);
+    key = (double)(tot + Di);
   } else if (lane == nf) {
     mask = xs;
     key = (double)tot;
   }
   wave_sort(key, mask, lane);
-  const double vk = readlane_f64(key, kp - 1);
+  double lkey = lane < kp ? key : __builtin_inf();
+  uint64_t lmask = lane < kp ? mask : ~0ull;
+  // two-flip neighbours x* ^ e_i ^ e_j (lane i < j < nf):
+  //   f = f(x*) + D_i + D_j + s_i s_j S_ij,  s = 1 - 2 x*
+  // so every K' up to 64 is backed once nf >= 11
+  for (int j = 1; j < nf; ++j) {
+    W Dj, sj;
+    if constexpr (std::is_same_v<W, double>) Dj = readlane_f64(Di, j);
+    else Dj = readlane_i64(Di, j);
+    sj = ((xs >> j) & 1) ? (W)-1 : (W)1;
+    const bool ok = lane < j;
+    const W sij = sw[(ok ? lane : 0) * np + j];
+    const double ck = ok ? (double)(tot + Di + Dj + si * sj * sij) : __builtin_inf();
+    const uint64_t cm = xs ^ (1ull << lane) ^ (1ull << j);
+    double tk = readlane_f64(lkey, kp - 1);
+    uint64_t tm = readlane_u64(lmask, kp - 1);
+    uint64_t bal = ballot(ok && before(ck, cm, tk, tm));
+    while (bal) {
+      const int src = __builtin_ctzll(bal);
+      bal &= bal - 1;
+      const double k2 = readlane_f64(ck, src);
+      const uint64_t m2 = readlane_u64(cm, src);
+      if (before(k2, m2, tk, tm)) {
+        list_insert(lkey, lmask, k2, m2, kp, lane);
+        tk = readlane_f64(lkey, kp - 1);
+        tm = readlane_u64(lmask, kp - 1);
+      }
+    }
+  }
+  const double vk = readlane_f64(lkey, kp - 1);
   if (lane == 0 && vk < __builtin_inf()) {
     // float: the walk's filter error (eps) plus float64 rounding of the sums here
     const double margin = std::is_same_v<W, double> ? I->eps + 1e-12 * I->sumabs : 0.0;
@@ -479,10 +558,12 @@ hipError_t launch_seed(const Views& v, int dt, hipStream_t s) {
   // padded n x n plus the diagonal, 8-byte exact entries (every path) and a float32 copy
   const size_t np = (size_t)((v.nmax + 3) & ~3);
   const size_t lds = (sizeof(double) + sizeof(float)) * (np * np + np);
+  // a single instance takes four waves of descents, a batch one per instance
+  const int threads = v.batch == 1 ? kSeedThreads : kWave;
   if (dt == kDtI32)
-    hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(64), lds, s, v);
+    hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(threads), lds, s, v);
   else
-    hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(64), lds, s, v);
+    hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(threads), lds, s, v);
   return hipGetLastError();
 }
 
