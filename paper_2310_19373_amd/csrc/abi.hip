@@ -331,9 +331,11 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
   HIPCHK(launch_prep_inst(v, Q, ldq, stride, dt, pp.inner, s));
   HIPCHK(launch_prep_lanes(v, dt, s));
-  // single small instances: the walk is shorter than the seed's latency.  A
-  // prefix-range solve seeds inside its range (the planner's seed_fix).
-  if (ns != nullptr || n_single > 22) HIPCHK(launch_seed(v, dt, s));
+  // single small instances: the walk is shorter than the seed's latency
+  // (measured crossover: n = 15 for float Q, whose K' = 2k lists start colder,
+  // n = 19 for integer Q).  A prefix-range solve seeds inside its range (the
+  // planner's seed_fix).
+  if (ns != nullptr || n_single >= (dt_exact(dt) ? 19 : 15)) HIPCHK(launch_seed(v, dt, s));
   HIPCHK(launch_prep_tables(v, dt, pp.inner, steps_hint, s));
   {
     ProfScope ps("walk_topk", s);

@@ -21,71 +21,42 @@ namespace qbf {
 
 namespace {
 
-template <class Qin>
-struct Rescore;
-template <>
-struct Rescore<float> {
-  using En = double;
-  __device__ static En sentinel() { return __builtin_inf(); }
-  __device__ static En energy(const float* Q, int ldq, int n, uint64_t m) {
-    double tot = 0.0;
-    for (int i = 0; i < n; ++i) {
-      if (!((m >> i) & 1)) continue;
-      double row = (double)Q[i * ldq + i];
-      for (int j = i + 1; j < n; ++j)
-        if ((m >> j) & 1) row = __dadd_rn(row, (double)Q[i * ldq + j]);
-      tot = __dadd_rn(tot, row);
-    }
-    return tot;
-  }
-};
-template <>
-struct Rescore<int32_t> {
-  using En = int64_t;
-  __device__ static En sentinel() { return INT64_MAX; }
-  __device__ static En energy(const int32_t* Q, int ldq, int n, uint64_t m) {
-    int64_t tot = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!((m >> i) & 1)) continue;
-      int64_t row = Q[i * ldq + i];
-      for (int j = i + 1; j < n; ++j)
-        if ((m >> j) & 1) row += Q[i * ldq + j];
-      tot += row;
-    }
-    return tot;
-  }
-};
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ int64_t add_rn(int64_t a, int64_t b) { return a + b; }
 
-template <>
-struct Rescore<double> {
-  using En = double;
-  __device__ static En sentinel() { return __builtin_inf(); }
-  __device__ static En energy(const double* Q, int ldq, int n, uint64_t m) {
-    double tot = 0.0;
-    for (int i = 0; i < n; ++i) {
-      if (!((m >> i) & 1)) continue;
-      double row = Q[i * ldq + i];
-      for (int j = i + 1; j < n; ++j)
-        if ((m >> j) & 1) row = __dadd_rn(row, Q[i * ldq + j]);
-      tot = __dadd_rn(tot, row);
+// Canonical-order energy: rows i ascending; a row term starts at Q_ii and adds
+// Q_ij for set j > i in ascending j; row terms are added in ascending i, in
+// En (float64 or int64).  A row's entries are read eight at a time ahead of
+// its additions, whose order is unchanged.
+template <class T, class En>
+__device__ __forceinline__ En canonical_energy(const T* Q, int ldq, int n, uint64_t m) {
+  En tot = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!((m >> i) & 1)) continue;
+    En row = (En)Q[i * ldq + i];
+    for (int j0 = i + 1; j0 < n; j0 += 8) {
+      T q[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) q[d] = j0 + d < n ? Q[i * ldq + j0 + d] : (T)0;
+#pragma unroll
+      for (int d = 0; d < 8; ++d)
+        if (j0 + d < n && ((m >> (j0 + d)) & 1)) row = add_rn(row, (En)q[d]);
     }
-    return tot;
+    tot = add_rn(tot, row);
   }
-};
-template <>
-struct Rescore<int64_t> {
-  using En = int64_t;
-  __device__ static En sentinel() { return INT64_MAX; }
-  __device__ static En energy(const int64_t* Q, int ldq, int n, uint64_t m) {
-    int64_t tot = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!((m >> i) & 1)) continue;
-      int64_t row = Q[i * ldq + i];
-      for (int j = i + 1; j < n; ++j)
-        if ((m >> j) & 1) row += Q[i * ldq + j];
-      tot += row;
-    }
-    return tot;
+  return tot;
+}
+
+// Output type and sentinel per input type.
+template <class Qin>
+struct Rescore {
+  using En = std::conditional_t<std::is_floating_point_v<Qin>, double, int64_t>;
+  __device__ static En sentinel() {
+    if constexpr (std::is_floating_point_v<Qin>) return __builtin_inf();
+    else return INT64_MAX;
+  }
+  __device__ static En energy(const Qin* Q, int ldq, int n, uint64_t m) {
+    return canonical_energy<Qin, En>(Q, ldq, n, m);
   }
 };
 

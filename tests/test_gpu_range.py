@@ -76,8 +76,8 @@ def test_n40_in_four_ranges_equals_full_solve(gpu_lib):
 @pytest.mark.parametrize("dtype,k,lo,hi", [("f32", 8, 1, 2), ("f32", 16, 3, 7), ("i32", 8, 9, 16),
                                           ("i32", 40, 0, 1)])
 def test_seeded_ranges_against_oracle(gpu_lib, dtype, k, lo, hi):
-    # n > 22: the threshold seed runs, confined to the range's first prefix
-    # (k = 40 leaves more candidates than the 22 free bits back: no seed)
+    # n = 26: the threshold seed runs, confined to the range's first prefix
+    # (k = 40, int: K' = 40 needs the two-flip neighbours of the 22 free bits)
     n, pb = 26, 4
     Q = inputs.random_f32(n, 510) if dtype == "f32" else inputs.random_i32(n, 511, -30, 30)
     print(f"seeded range {dtype} k={k} [{lo},{hi}) of 2^{pb}", flush=True)
