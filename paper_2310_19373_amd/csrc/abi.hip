@@ -330,13 +330,12 @@ int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const i
   pp.waves = waves;
   HIPCHK(launch_plan(v, ns, n_single, nullptr, pp, s));
   HIPCHK(launch_prep_inst(v, Q, ldq, stride, dt, pp.inner, s));
-  HIPCHK(launch_prep_lanes(v, dt, s));
   // single small instances: the walk is shorter than the seed's latency
   // (measured crossover: n = 15 for float Q, whose K' = 2k lists start colder,
   // n = 19 for integer Q).  A prefix-range solve seeds inside its range (the
   // planner's seed_fix).
-  if (ns != nullptr || n_single >= (dt_exact(dt) ? 19 : 15)) HIPCHK(launch_seed(v, dt, s));
-  HIPCHK(launch_prep_tables(v, dt, pp.inner, steps_hint, s));
+  const bool seed = ns != nullptr || n_single >= (dt_exact(dt) ? 19 : 15);
+  HIPCHK(launch_prep_walk(v, dt, pp.inner, steps_hint, seed, s));
   {
     ProfScope ps("walk_topk", s);
     HIPCHK(launch_walk_topk(v, dt, waves, s));
@@ -555,8 +554,7 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, kDtF32, kInner, s));
-  HIPCHK(launch_prep_lanes(v, kDtF32, s));
-  HIPCHK(launch_prep_tables(v, kDtF32, kInner, steps_bound, s));
+  HIPCHK(launch_prep_walk(v, kDtF32, kInner, steps_bound, false, s));
   HIPCHK(launch_prep_exp_tables(v, beta, kInner, steps_bound, s));
   {
     ProfScope ps("walk_exp", s);
@@ -586,8 +584,7 @@ static int run_moment_walk(int batch, const float* Q, int nmax, const int32_t* n
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, kDtF32, pp.inner, s));
-  HIPCHK(launch_prep_lanes(v, kDtF32, s));
-  HIPCHK(launch_prep_tables(v, kDtF32, pp.inner, steps_bound, s));
+  HIPCHK(launch_prep_walk(v, kDtF32, pp.inner, steps_bound, false, s));
   HIPCHK(launch_prep_exp_tables(v, beta, pp.inner, steps_bound, s));
   {
     ProfScope ps("walk_grad", s);
@@ -643,8 +640,7 @@ int qubo_logz_sample(int batch, const float* Q, int nmax, const int32_t* ns, con
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));
   HIPCHK(launch_prep_inst(v, Q, nmax, (int64_t)nmax * nmax, kDtF32, kInner, s));
-  HIPCHK(launch_prep_lanes(v, kDtF32, s));
-  HIPCHK(launch_prep_tables(v, kDtF32, kInner, steps_bound, s));
+  HIPCHK(launch_prep_walk(v, kDtF32, kInner, steps_bound, false, s));
   HIPCHK(launch_prep_exp_tables(v, beta, kInner, steps_bound, s));
   HIPCHK(launch_walk_exp(v, beta, waves, s));
   HIPCHK(launch_finalize_logz(v, beta, logz, status, s));

@@ -22,7 +22,7 @@ struct Views {
   int32_t* eoi;    // [total_steps] -E_O(g(t)), dense (int path)
   Slot* slots;     // [total_slots][kprime]
   double* part;    // per-unit partial sums (logZ forward) / per-wave moments (gradient)
-  void* lt;        // [batch][64][kLaneRec] lane table (double or int64), see prep_lanes
+  void* lt;        // [batch][64][kLaneRec] lane table (double or int64), see launch_prep_walk
   uint32_t* umap;  // [umap_cap] work unit -> instance, or null (binary search)
   void* etab;      // log-partition: factor table b(t, j), layout of tab (float), or null
   double* tref;    // log-partition: min_j T'(g(t); j) + E_O(g(t)) per step, or null
@@ -58,14 +58,13 @@ hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const fl
 // dt: one of kDt* (the log-partition paths pass kDtF32).
 hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, int dt,
                             int inner, hipStream_t s);
-// per-instance lane table: contributions of the lane bits to E_P and to the
-// inner / outer cross fields, for each of the 64 lane values.
-hipError_t launch_prep_lanes(const Views& v, int dt, hipStream_t s);
-// a-priori threshold per instance from a greedy descent (after prep_inst).
-hipError_t launch_seed(const Views& v, int dt, hipStream_t s);
-// per-step tables of the outer walk; steps_bound >= total steps of the plan
-// (sizes the grid only: the kernel reads the exact count from the header).
-hipError_t launch_prep_tables(const Views& v, int dt, int inner, int64_t steps_bound, hipStream_t s);
+// the per-instance inputs of the walks, after prep_inst, in one launch: the
+// lane table (contributions of the lane bits to E_P and to the inner / outer
+// cross fields, for each of the 64 lane values), the per-step tables of the
+// outer walk and, when `seed`, the a-priori threshold from a greedy descent.
+// steps_bound >= total steps of the plan (sizes the grid only: the kernel
+// reads the exact counts from the instances).
+hipError_t launch_prep_walk(const Views& v, int dt, int inner, int64_t steps_bound, bool seed, hipStream_t s);
 // persistent top-k walk.
 hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s);
 // merge candidate lists, rescore in float64 / int64, certificate, outputs.
@@ -76,7 +75,7 @@ hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int6
 // merge of top-k lists from disjoint prefix ranges of one instance (one wave).
 hipError_t launch_merge_topk(int count, int k_in, const void* ein, const uint64_t* min, int dt, int k, void* eout,
                              uint64_t* mout, hipStream_t s);
-// log-partition: factor tables (after prep_tables), forward walk, finalize.
+// log-partition: factor tables (after launch_prep_walk), forward walk, finalize.
 hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, int64_t steps_bound,
                                  hipStream_t s);
 hipError_t launch_walk_exp(const Views& v, const float* beta, int waves, hipStream_t s);

@@ -6,7 +6,9 @@
 // prep_inst      : symmetric copy of Q (the qua/lin split of Sec. 3: off-diagonal
 //                  S = triu(Q,1) + triu(Q,1)^T, diagonal d = diag(Q)), sum |Q|,
 //                  validation, and the inner-bit energies E_I(j).
-// prep_tables    : per outer Gray step t the uniform table T'(g(t); j) and the
+// prep_walk      : one launch of three independent roles per instance: the
+//                  threshold seed (greedy descents), the lane table, and per
+//                  outer Gray step t the uniform table T'(g(t); j) with the
 //                  scalars E_O(g(t)), H_u(g(t)).
 #include <math.h>
 
@@ -231,8 +233,7 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
 // S(u, a) for inner bits u, [8+k] = sum_{set lane bits a} S(B+k, a) for outer
 // bits k.
 template <class W>
-__global__ void __launch_bounds__(64) prep_lanes_kernel(Views v) {
-  const int b = blockIdx.x, l = threadIdx.x;
+__device__ void lanes_role(const Views& v, int b, int l) {
   const Inst* I = &v.inst[b];
   W* lt = (W*)v.lt + ((int64_t)b * 64 + l) * kLaneRec;
   W rec[kLaneRec];
@@ -310,11 +311,10 @@ constexpr int kSeedThreads = 256;  // descents of a single instance (one per thr
 // so lane i evaluates one field of x* and the wave sums: O(n) per lane; a
 // two-flip value adds s_i s_j S_ij (s = 1 - 2x) to the two one-flip changes.
 template <class W>
-__global__ void __launch_bounds__(kSeedThreads) seed_kernel(Views v) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char seed_lds[];
+__device__ void seed_role(const Views& v, int b, unsigned char* seed_lds) {
   __shared__ float best_f[kSeedThreads / kWave];
   __shared__ uint64_t best_x[kSeedThreads / kWave];
-  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nt = blockDim.x, nwv = nt >> 6;
   const Inst* I = &v.inst[b];
   if (I->status != 0) return;  // uniform over the block
@@ -449,20 +449,19 @@ __global__ void __launch_bounds__(kSeedThreads) seed_kernel(Views v) {
 }
 
 template <class W, class E>
-__global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
-  // blockIdx.x: instance; blockIdx.y: chunk of 256 of its steps.  The entries
-  // the step scalars need -- S(u, B+l) for inner u and S(B+l, B+l2) for outer
-  // l, l2 -- are staged in LDS.  A wave takes 64 consecutive steps: lane i
-  // computes the scalars of step s0 + i, parks H in LDS, and the wave then
-  // writes the 64 table rows one coalesced row at a time.
-  __shared__ W hs[4][6][kWave];
-  __shared__ W qo[(6 + kMaxOuter) * kMaxOuter];
-  const int b = blockIdx.x;
+__device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigned char* lds) {
+  // chunk: blockDim.x consecutive steps of instance b.  The entries the step
+  // scalars need -- S(u, B+l) for inner u and S(B+l, B+l2) for outer l, l2 --
+  // are staged in LDS.  A wave takes 64 consecutive steps: lane i computes the
+  // scalars of step s0 + i, parks H in LDS, and the wave then writes the 64
+  // table rows one coalesced row at a time.
+  W(*hs)[6][kWave] = (W(*)[6][kWave])lds;  // [waves][6][64]
+  W* qo = (W*)(lds + sizeof(W) * (blockDim.x / kWave) * 6 * kWave);
   const Inst* I = &v.inst[b];
   if (I->status != 0) return;  // the walks skip such instances
   const int B = I->B, no = I->no, nm = v.nmax;
   const int64_t steps = int64_t(1) << no;
-  const int64_t c0 = (int64_t)blockIdx.y * 256;
+  const int64_t c0 = (int64_t)chunk * blockDim.x;
   if (c0 >= steps) return;
   const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
   // row r < 6: inner row u = r; row 6 + l: outer row B + l; column l2: B + l2
@@ -514,6 +513,23 @@ __global__ void __launch_bounds__(256) prep_tables_kernel(Views v, int inner) {
   }
 }
 
+// The per-instance inputs of a walk, in one launch: blockIdx.x is the
+// instance; blockIdx.y = 0 the threshold seed (when seed_on), 1 the lane
+// table, 2 + c the step tables of chunk c.  The three only read what
+// prep_inst wrote, so their latencies overlap.
+template <class W, class E>
+__global__ void __launch_bounds__(kSeedThreads) prep_walk_kernel(Views v, int inner, int seed_on) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char prep_lds[];
+  const int b = blockIdx.x, role = blockIdx.y;
+  if (role == 0) {
+    if (seed_on) seed_role<W>(v, b, prep_lds);
+  } else if (role == 1) {
+    if (threadIdx.x < kWave) lanes_role<W>(v, b, threadIdx.x);
+  } else {
+    tables_role<W, E>(v, b, role - 2, inner, prep_lds);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_plan(const Views& v, const int32_t* ns, int n_single, const float* beta, const PlanParams& pp,
@@ -545,39 +561,26 @@ hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_prep_lanes(const Views& v, int dt, hipStream_t s) {
-  if (dt == kDtI32)
-    hipLaunchKernelGGL(prep_lanes_kernel<int64_t>, dim3(v.batch), dim3(64), 0, s, v);
-  else
-    hipLaunchKernelGGL(prep_lanes_kernel<double>, dim3(v.batch), dim3(64), 0, s, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_seed(const Views& v, int dt, hipStream_t s) {
-  if (v.seed_sweeps <= 0) return hipSuccess;  // seeding switched off
-  // padded n x n plus the diagonal, 8-byte exact entries (every path) and a float32 copy
+hipError_t launch_prep_walk(const Views& v, int dt, int inner, int64_t steps_bound, bool seed, hipStream_t s) {
+  // a single instance: 256 threads (four waves of seed descents, 256 steps
+  // per table block); a batch: one wave per block
+  const int T = v.batch == 1 ? kSeedThreads : kWave;
+  const int64_t per_inst = (steps_bound + v.batch - 1) / v.batch;  // steps of one instance, bound
+  const int64_t chunks = (per_inst + T - 1) / T > 0 ? (per_inst + T - 1) / T : 1;
+  const dim3 grid((unsigned)v.batch, (unsigned)(2 + chunks));
+  const bool seed_on = seed && v.seed_sweeps > 0;
+  // dynamic LDS: the seed's padded n x n (8-byte exact + float32 copies) and
+  // diagonal, or the tables' staging, whichever is larger
   const size_t np = (size_t)((v.nmax + 3) & ~3);
-  const size_t lds = (sizeof(double) + sizeof(float)) * (np * np + np);
-  // a single instance takes four waves of descents, a batch one per instance
-  const int threads = v.batch == 1 ? kSeedThreads : kWave;
+  const size_t seed_bytes = seed_on ? (sizeof(double) + sizeof(float)) * (np * np + np) : 0;
+  const size_t tab_bytes = sizeof(double) * ((size_t)(T / kWave) * 6 * kWave + (6 + kMaxOuter) * kMaxOuter);
+  const size_t lds = seed_bytes > tab_bytes ? seed_bytes : tab_bytes;
   if (dt == kDtI32)
-    hipLaunchKernelGGL(seed_kernel<int64_t>, dim3(v.batch), dim3(threads), lds, s, v);
-  else
-    hipLaunchKernelGGL(seed_kernel<double>, dim3(v.batch), dim3(threads), lds, s, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_prep_tables(const Views& v, int dt, int inner, int64_t steps_bound, hipStream_t s) {
-  // one block per (instance, chunk of 256 steps); steps_bound / batch bounds
-  // the steps of one instance
-  const int64_t per_inst = (steps_bound + v.batch - 1) / v.batch;
-  const dim3 grid((unsigned)v.batch, (unsigned)((per_inst + 255) / 256 > 0 ? (per_inst + 255) / 256 : 1));
-  if (dt == kDtI32)
-    hipLaunchKernelGGL((prep_tables_kernel<int64_t, int32_t>), grid, dim3(256), 0, s, v, inner);
+    hipLaunchKernelGGL((prep_walk_kernel<int64_t, int32_t>), grid, dim3(T), lds, s, v, inner, (int)seed_on);
   else if (dt_wide(dt))
-    hipLaunchKernelGGL((prep_tables_kernel<double, double>), grid, dim3(256), 0, s, v, inner);
+    hipLaunchKernelGGL((prep_walk_kernel<double, double>), grid, dim3(T), lds, s, v, inner, (int)seed_on);
   else
-    hipLaunchKernelGGL((prep_tables_kernel<double, float>), grid, dim3(256), 0, s, v, inner);
+    hipLaunchKernelGGL((prep_walk_kernel<double, float>), grid, dim3(T), lds, s, v, inner, (int)seed_on);
   return hipGetLastError();
 }
 
