@@ -2,11 +2,14 @@
 //
 // One block per instance (W waves).  Each wave scans a share of the instance's
 // flushed lists, keeping its own sorted top-K' (filtered by the instance's
-// published threshold, which bounds the final K'-th key from above); wave 0
-// merges the others through LDS.  Wave 0 then recomputes every candidate's
-// energy from the input Q in a fixed order -- i ascending; for each set bit i
-// the row term starts at Q_ii and adds Q_ij for set j > i in ascending j; row
-// terms summed in ascending i -- in float64 (float Q) or int64 (int Q), sorts
+// published threshold, which bounds the final K'-th key from above; a chunk
+// with many qualifying entries is sorted and merged by bitonic networks, a
+// few are inserted one by one); the waves' lists are merged pairwise through
+// LDS.  Every candidate's energy is then recomputed from the input Q in a
+// fixed order -- i ascending; for each set bit i the row term starts at Q_ii
+// and adds Q_ij for set j > i in ascending j; row terms summed in ascending i
+// -- in float64 (float Q) or int64 (int Q), spread over the waves (one lane per
+// row) when there are four or more, else one lane per candidate.  Wave 0 sorts
 // by (energy, mask), writes the k best and, for float Q, checks the
 // certificate: every state outside the candidate set has an exact value of at
 // least thr - eps, where thr is the K'-th candidate key, so the selection is
@@ -24,27 +27,52 @@ namespace {
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 __device__ __forceinline__ int64_t add_rn(int64_t a, int64_t b) { return a + b; }
 
-// Canonical-order energy: rows i ascending; a row term starts at Q_ii and adds
-// Q_ij for set j > i in ascending j; row terms are added in ascending i, in
-// En (float64 or int64).  A row's entries are read eight at a time ahead of
-// its additions, whose order is unchanged.
+// Row term of the canonical order: Q_ii, then Q_ij for set j > i in ascending
+// j, in En.  A row's entries are read eight at a time ahead of its additions,
+// whose order is unchanged.
+template <class T, class En>
+__device__ __forceinline__ En row_term(const T* Q, int ldq, int n, int i, uint64_t m) {
+  En row = (En)Q[i * ldq + i];
+  for (int j0 = i + 1; j0 < n; j0 += 8) {
+    T q[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) q[d] = j0 + d < n ? Q[i * ldq + j0 + d] : (T)0;
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+      if (j0 + d < n && ((m >> (j0 + d)) & 1)) row = add_rn(row, (En)q[d]);
+  }
+  return row;
+}
+
+// Canonical-order energy: row terms of the set rows added in ascending i, in
+// En (float64 or int64).
 template <class T, class En>
 __device__ __forceinline__ En canonical_energy(const T* Q, int ldq, int n, uint64_t m) {
   En tot = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!((m >> i) & 1)) continue;
-    En row = (En)Q[i * ldq + i];
-    for (int j0 = i + 1; j0 < n; j0 += 8) {
-      T q[8];
-#pragma unroll
-      for (int d = 0; d < 8; ++d) q[d] = j0 + d < n ? Q[i * ldq + j0 + d] : (T)0;
-#pragma unroll
-      for (int d = 0; d < 8; ++d)
-        if (j0 + d < n && ((m >> (j0 + d)) & 1)) row = add_rn(row, (En)q[d]);
-    }
-    tot = add_rn(tot, row);
-  }
+  for (int i = 0; i < n; ++i)
+    if ((m >> i) & 1) tot = add_rn(tot, row_term<T, En>(Q, ldq, n, i, m));
   return tot;
+}
+
+// Bitonic merge of two wave lists, each ascending by (key, mask) over the 64
+// lanes, into the 64 smallest entries of their union, ascending.
+__device__ __forceinline__ void merge64(double& ak, uint64_t& am, double bk, uint64_t bm, int lane) {
+  const double rk = __shfl(bk, kWave - 1 - lane);
+  const uint64_t rm = __shfl(bm, kWave - 1 - lane);
+  if (before(rk, rm, ak, am)) {  // lane-wise minimum of a and reversed b: bitonic
+    ak = rk;
+    am = rm;
+  }
+#pragma unroll
+  for (int j = kWave / 2; j > 0; j >>= 1) {
+    const double pk = __shfl_xor(ak, j);
+    const uint64_t pm = __shfl_xor(am, j);
+    const bool lower = (lane & j) == 0;
+    if (lower ? before(pk, pm, ak, am) : before(ak, am, pk, pm)) {
+      ak = pk;
+      am = pm;
+    }
+  }
 }
 
 // Output type and sentinel per input type.
@@ -73,6 +101,7 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   __shared__ double sk[kMaxFinWaves][kWave];
   __shared__ uint64_t sm[kMaxFinWaves][kWave];
   __shared__ Qin sq[64 * 64];  // the instance's n x n block, row stride n
+  __shared__ En se[kMaxKPrime];
   const int b = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const Inst* I = &v.inst[b];
@@ -94,6 +123,22 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
         m = sl[e].mask;
       }
       uint64_t bal = ballot(key <= thr);
+      if (__popcll(bal) > 8) {
+        // many candidates: sort them and merge (two bitonic networks) rather
+        // than insert one at a time
+        const bool c = key <= thr;
+        double ck = c ? key : __builtin_inf();
+        uint64_t cm = c ? m : ~0ull;
+        wave_sort(ck, cm, lane);
+        merge64(lkey, lmask, ck, cm, lane);
+        if (lane >= kp) {
+          lkey = __builtin_inf();
+          lmask = ~0ull;
+        }
+        const double lt = readlane_f64(lkey, kp - 1);
+        if (lt < thr) thr = lt;
+        continue;
+      }
       while (bal) {
         const int src = __builtin_ctzll(bal);
         bal &= bal - 1;
@@ -107,40 +152,60 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
   }
   sk[w][lane] = lkey;
   sm[w][lane] = lmask;
+  const int n = I->n;
   if (st0 == 0) {
-    const int n = I->n;
     const Qin* Qb = q + (int64_t)b * stride;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) sq[e] = Qb[(int64_t)(e / n) * ldq + e % n];
   }
   __syncthreads();
-  if (w != 0) return;
-  // the other waves' sorted lists: only entries before the current K'-th can
-  // enter, and once one fails the rest of that list fails too
-  for (int o = 1; o < nw; ++o) {
-    const double ok = sk[o][lane];
-    const uint64_t om = sm[o][lane];
-    double tk = readlane_f64(lkey, kp - 1);
-    uint64_t tm = readlane_u64(lmask, kp - 1);
-    uint64_t bal = ballot(lane < kp && ok < __builtin_inf() && before(ok, om, tk, tm));
-    while (bal) {
-      const int src = __builtin_ctzll(bal);
-      bal &= bal - 1;
-      const double ck = readlane_f64(ok, src);
-      const uint64_t cm = readlane_u64(om, src);
-      if (!before(ck, cm, tk, tm)) break;
-      list_insert(lkey, lmask, ck, cm, kp, lane);
-      tk = readlane_f64(lkey, kp - 1);
-      tm = readlane_u64(lmask, kp - 1);
+  // the waves' lists, merged pairwise in log2(waves) rounds; sk[0] ends with
+  // the K' best
+  for (int r = 1; r < nw; r <<= 1) {
+    if ((w & (2 * r - 1)) == 0 && w + r < nw) {
+      merge64(lkey, lmask, sk[w + r][lane], sm[w + r][lane], lane);
+      if (lane >= kp) {
+        lkey = __builtin_inf();
+        lmask = ~0ull;
+      }
+      sk[w][lane] = lkey;
+      sm[w][lane] = lmask;
+    }
+    __syncthreads();
+  }
+  En en = Rescore<Qin>::sentinel();
+  uint64_t m = ~0ull;
+  if (nw >= 4) {
+    // rescoring spread over the waves: wave w takes candidates w, w + nw, ...;
+    // lane i computes row i's term and the wave adds the set rows' terms in
+    // ascending i (the canonical order)
+    for (int c = w; c < kp; c += nw) {
+      const double ckey = sk[0][c];
+      const uint64_t cm = sm[0][c];
+      En tot = Rescore<Qin>::sentinel();
+      if (st0 == 0 && ckey < __builtin_inf()) {
+        En r = 0;
+        if (lane < n && ((cm >> lane) & 1)) r = row_term<Qin, En>(sq, n, n, lane, cm);
+        tot = 0;
+        for (int i = 0; i < n; ++i)
+          if ((cm >> i) & 1) tot = add_rn(tot, readlane_en(r, i));
+      }
+      if (lane == 0) se[c] = tot;
+    }
+    __syncthreads();
+    if (w != 0) return;
+    if (st0 == 0 && lane < kp && lkey < __builtin_inf()) {
+      m = lmask;
+      en = se[lane];
+    }
+  } else {
+    if (w != 0) return;
+    if (st0 == 0 && lane < kp && lkey < __builtin_inf()) {
+      m = lmask;
+      en = Rescore<Qin>::energy(sq, n, n, m);
     }
   }
   int32_t st = st0;
   if (st == 0 && (int64_t)v.flushcnt[b] > I->slot_cap) st = kErrOverflow;
-  En en = Rescore<Qin>::sentinel();
-  uint64_t m = ~0ull;
-  if (st0 == 0 && lane < kp && lkey < __builtin_inf()) {
-    m = lmask;
-    en = Rescore<Qin>::energy(sq, I->n, I->n, m);
-  }
   wave_sort(en, m, lane);
   if constexpr (std::is_floating_point_v<Qin>) {
     const double thr_m = readlane_f64(lkey, kp - 1);
