@@ -908,14 +908,22 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* be
     const double lz2 = uniform_f64(logz[b]) * kLog2e;
     double ur = uniform_f64(uin[id]);
     ur = ur > 0.0 ? (ur < 1.0 ? ur : 0x1.fffffffffffffp-1) : 0.0;  // NaN -> 0
-    // 1. unit: the first whose running sum exceeds t
+    // 1. unit: the first whose running sum exceeds t (the last if rounding
+    // left none), 64 probes per round: lane q reads the last running sum of
+    // block q of the remaining range, and the first block over t is kept
     const double* cb = cum + I.unit_begin;
     double t = ur * uniform_f64(cb[units - 1]);
-    int64_t lo = 0, hi = units - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (uniform_f64(cb[mid]) > t) hi = mid;
-      else lo = mid + 1;
+    int64_t lo = 0, hi = units;  // the unit lies in [lo, hi)
+    while (hi - lo > 1) {
+      const int64_t stride = (hi - lo + kWave - 1) / kWave;
+      int64_t idx = lo + (int64_t)(lane + 1) * stride - 1;
+      if (idx > hi - 1) idx = hi - 1;
+      const uint64_t over = ballot(cb[idx] > t);
+      const int nblk = (int)((hi - lo + stride - 1) / stride);
+      const int q = over ? __builtin_ctzll(over) : nblk - 1;
+      const int64_t nlo = lo + (int64_t)q * stride;
+      hi = nlo + stride < hi ? nlo + stride : hi;
+      lo = nlo;
     }
     const double c0 = lo > 0 ? uniform_f64(cb[lo - 1]) : 0.0;
     double wp = uniform_f64(cb[lo]) - c0;  // weight of the chosen entry
