@@ -125,3 +125,32 @@ def test_f64_ranges_merge_to_full(gpu_lib):
     me, mm = api.merge_topk(parts, k)
     fe, fm = api.solve(Q, k)
     assert torch.equal(me, fe) and torch.equal(mm, fm)
+
+
+@pytest.mark.parametrize("dt,npdt", [(_lib.QUBO_F32, np.float32), (_lib.QUBO_I32, np.int32),
+                                     (_lib.QUBO_F64, np.float64), (_lib.QUBO_I64, np.int64)])
+def test_leading_dimension_larger_than_n(gpu_lib, dt, npdt):
+    # Q stored with row stride ldq = n + 5 (garbage in the padding columns and
+    # in the lower triangle): the C ABI reads only i <= j < n of each row
+    n, k, ldq = 21, 6, 26
+    rng = np.random.default_rng(1700 + dt)
+    if np.issubdtype(npdt, np.integer):
+        Q = np.triu(rng.integers(-50, 51, (n, n))).astype(npdt)
+    else:
+        Q = np.triu(rng.standard_normal((n, n))).astype(npdt)
+    big = np.full((n, ldq), 7 if np.issubdtype(npdt, np.integer) else np.nan, dtype=npdt)
+    big[:, :n] = Q + np.tril(np.ones((n, n), dtype=npdt), -1) * 3
+    Qd = torch.from_numpy(big).cuda()
+    L = _lib.lib()
+    wsb = L.qubo_bf_workspace_size(n, k, dt)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    en = torch.empty(k, dtype=torch.float64 if dt in (_lib.QUBO_F32, _lib.QUBO_F64) else torch.int64, device="cuda")
+    mk = torch.empty(k, dtype=torch.int64, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, ldq, dt, k, en.data_ptr(), mk.data_ptr(), st.data_ptr(),
+                               ws.data_ptr(), wsb, None))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    E, M = oracle.topk(Q, k)
+    assert _u64(_np(mk)) == _u64(M)
+    assert np.array_equal(_np(en), E)
