@@ -63,7 +63,7 @@ typedef enum { QUBO_F32 = 0, QUBO_I32 = 1, QUBO_F64 = 2, QUBO_I64 = 3 } qubo_dty
 enum {
   QUBO_OK = 0,
   QUBO_ERR_INVALID_ARG = -1, /* bad argument (host) or bad n in ns (device status) */
-  QUBO_ERR_NONFINITE = -2,   /* Q holds inf or NaN (device status) */
+  QUBO_ERR_NONFINITE = -2,   /* Q (or beta) holds inf or NaN (device status) */
   QUBO_ERR_WORKSPACE = -3,   /* ws_bytes smaller than the workspace query */
   QUBO_ERR_HIP = -4,         /* a HIP launch or runtime call failed */
   QUBO_ERR_UNCERTAIN = -5,   /* float certificate failed (device status) */
@@ -151,7 +151,8 @@ size_t qubo_logz_workspace_size(int batch, int nmax);
  * logZ_b = log sum_x exp(-beta_b f_{Q_b}(x)), natural log, float64 result.
  *   Q      device, [batch][nmax][nmax] float32, sizes ns (device, [batch])
  *   nmax   1 .. 32
- *   beta   device, [batch] float32, any finite value
+ *   beta   device, [batch] float32, any finite value (else that instance's
+ *          status is QUBO_ERR_NONFINITE and its logz NaN)
  *   logz   device, [batch] double
  *   status device, [batch]
  */

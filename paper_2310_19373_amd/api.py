@@ -27,7 +27,7 @@ class UncertainError(QuboError):
 
 _STATUS = {
     _lib.QUBO_ERR_INVALID_ARG: "invalid instance size",
-    _lib.QUBO_ERR_NONFINITE: "Q holds inf or NaN",
+    _lib.QUBO_ERR_NONFINITE: "Q or beta holds inf or NaN",
     _lib.QUBO_ERR_UNCERTAIN: "float certificate failed",
     _lib.QUBO_ERR_RANGE: "integer Q with sum |Q_ij| beyond the walk's exact range (2^28 int32, 2^50 int64)",
     _lib.QUBO_ERR_OVERFLOW: "internal candidate slot overflow",

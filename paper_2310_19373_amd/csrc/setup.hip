@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
       I.units = s.units;
       I.unit_begin = cu;
       I.local_off = pp.range_bits > 0 ? pp.range_begin << (s.tb - pp.range_bits) : 0;
+      if (beta && !isfinite(beta[b])) I.status = kErrNonfinite;  // the walks skip the instance
       I.seed_fix = pp.range_bits > 0 ? pp.range_bits : 0;
       if (pp.range_bits > s.tb) I.status = kErrArg;  // the host checks this; kept as a guard
       I.tab_off = cs;

@@ -163,3 +163,29 @@ def test_logz_config_sample(gpu_lib):
     off = M[:, iu[0], iu[1]]
     assert np.all(off >= -1e-6)
     assert np.all(off <= np.minimum(d[:, iu[0]], d[:, iu[1]]) + 1e-6)
+
+
+def test_nonfinite_beta_flags_only_that_instance(gpu_lib):
+    # beta = NaN or inf: that instance's status is QUBO_ERR_NONFINITE and its
+    # logZ NaN; the other instances of the batch are unaffected
+    from paper_2310_19373_amd import _lib
+
+    batch, n = 4, 10
+    Q = np.stack([inputs.random_f32(n, 1800 + b, scale=0.3) for b in range(batch)])
+    betas = np.array([1.0, np.nan, np.inf, -0.5], dtype=np.float32)
+    Qd = torch.from_numpy(Q).cuda()
+    bd = torch.from_numpy(betas).cuda()
+    nsd = torch.full((batch,), n, dtype=torch.int32, device="cuda")
+    L = _lib.lib()
+    wsb = L.qubo_logz_workspace_size(batch, n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    lz = torch.empty(batch, dtype=torch.float64, device="cuda")
+    st = torch.empty(batch, dtype=torch.int32, device="cuda")
+    _lib.check(L.qubo_logz_fwd(batch, Qd.data_ptr(), n, nsd.data_ptr(), bd.data_ptr(), lz.data_ptr(), st.data_ptr(),
+                               ws.data_ptr(), wsb, None))
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [0, _lib.QUBO_ERR_NONFINITE, _lib.QUBO_ERR_NONFINITE, 0]
+    lz = lz.cpu().numpy()
+    assert np.isnan(lz[1]) and np.isnan(lz[2])
+    for b in (0, 3):
+        assert abs(lz[b] - oracle.logz(Q[b], float(betas[b]))) <= logz_tol(Q[b], float(betas[b]))
