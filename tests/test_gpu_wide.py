@@ -154,3 +154,11 @@ def test_leading_dimension_larger_than_n(gpu_lib, dt, npdt):
     E, M = oracle.topk(Q, k)
     assert _u64(_np(mk)) == _u64(M)
     assert np.array_equal(_np(en), E)
+
+
+def test_f64_nonfinite_is_reported(gpu_lib):
+    Q = _f64(9, 1900)
+    Q[2, 7] = np.inf
+    with pytest.raises(_lib.QuboError) as ei:
+        api.solve(Q, 2)
+    assert ei.value.code == _lib.QUBO_ERR_NONFINITE
