@@ -884,16 +884,14 @@ __device__ __forceinline__ double rescale(double t, double wp, double wc) {
 // own total: each level inverts its own distribution exactly, and the sampled
 // mask differs from the exact inverse only where u lies within the weights'
 // rounding of a boundary.
-__global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* beta, const double* logz,
-                                                       const double* cum, int nsamples, const double* uin,
-                                                       uint64_t* mout) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+sample_kernel(Views v, const float* beta, const double* logz, const double* cum, int nsamples, const double* uin,
+              uint64_t* mout) {
   __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
   __shared__ double bw[kWavesPerBlock][1 << kSampleOuter];
-  __shared__ float cq[kWavesPerBlock][kInnerStates];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* myc = ctab[w];
   double* myw = bw[w];
-  float* myq = cq[w];
   const int64_t total = (int64_t)v.batch * nsamples;
   for (int64_t id = (int64_t)blockIdx.x * kWavesPerBlock + w; id < total;
        id += (int64_t)gridDim.x * kWavesPerBlock) {
@@ -937,20 +935,25 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* be
     const int ls = pick_lane(lw, lincl, t);
     t -= readlane_f64(lincl - lw, ls);
     wp = readlane_f64(lw, ls);
-    // 3. outer value.  Lane ls's C' goes to LDS in the step tables' entry
-    // order (entry 4 (j mod 16) + j / 16 holds inner state j).
+    // 3. outer value.  Every lane takes lane ls's C' into registers in the
+    // step tables' entry order (entry 4 (j mod 16) + j / 16 holds inner state
+    // j) and its outer cross fields c_l.
     const bool valid = lane < (1 << I.L);
     float C[kInnerStates];
     const double EP = lane_init<float, kInnerStates>(v, b, I, local, valid, myc, lane, C);
+    float cr[kInnerStates];
     float cj = 0.f;
 #pragma unroll
     for (int j = 0; j < kInnerStates; ++j) {
       const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(C[j]), ls));
+      cr[4 * (j & 15) + (j >> 4)] = x;
       if (lane == j) cj = x;
     }
-    myq[4 * (lane & 15) + (lane >> 4)] = cj;
     const double EPs = readlane_f64(EP, ls);
     __builtin_amdgcn_wave_barrier();
+    double cl[kSampleOuter];
+#pragma unroll
+    for (int l = 0; l < kSampleOuter; ++l) cl[l] = l < I.no ? myc[l * kWave + ls] : 0.0;
     const float nb = bb > 0.0 ? (float)-bb : -1e-30f;  // beta = 0: sentinels still weigh 0
     const uint32_t steps = 1u << I.no;
     const gptr<const f32x4> tab4 = gp((const f32x4*)v.tab) + I.tab_off * (kInnerStates / 4);
@@ -958,18 +961,19 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* be
     for (uint32_t st = lane; st < steps; st += kWave) {
       const uint32_t o = (uint32_t)gray(st);
       double K = EPs + eod[st];
-      for (int l = 0; l < I.no; ++l)
-        if ((o >> l) & 1) K += myc[l * kWave + ls];
+#pragma unroll
+      for (int l = 0; l < kSampleOuter; ++l)
+        if ((o >> l) & 1) K += cl[l];
       const float cst = (float)(-bb * K - lz2);
       const gptr<const f32x4> row = tab4 + (int64_t)st * (kInnerStates / 4);
       float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < kInnerStates / 4; ++q) {
         const f32x4 tq = row[q];
-        acc[0] += exp2_fast(__builtin_fmaf(myq[4 * q + 0] + tq.x, nb, cst));
-        acc[1] += exp2_fast(__builtin_fmaf(myq[4 * q + 1] + tq.y, nb, cst));
-        acc[2] += exp2_fast(__builtin_fmaf(myq[4 * q + 2] + tq.z, nb, cst));
-        acc[3] += exp2_fast(__builtin_fmaf(myq[4 * q + 3] + tq.w, nb, cst));
+        acc[0] += exp2_fast(__builtin_fmaf(cr[4 * q + 0] + tq.x, nb, cst));
+        acc[1] += exp2_fast(__builtin_fmaf(cr[4 * q + 1] + tq.y, nb, cst));
+        acc[2] += exp2_fast(__builtin_fmaf(cr[4 * q + 2] + tq.z, nb, cst));
+        acc[3] += exp2_fast(__builtin_fmaf(cr[4 * q + 3] + tq.w, nb, cst));
       }
       myw[o] = (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
@@ -1011,8 +1015,9 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* be
     uint32_t ts = os;  // step with g(ts) = os
     for (int sh = 1; sh < 32; sh <<= 1) ts ^= ts >> sh;
     double Kb = EPs + uniform_f64(eod[ts]);
-    for (int l = 0; l < I.no; ++l)
-      if ((os >> l) & 1) Kb += myc[l * kWave + ls];
+#pragma unroll
+    for (int l = 0; l < kSampleOuter; ++l)
+      if ((os >> l) & 1) Kb += cl[l];
     const float tj = gp((const float*)v.tab)[(I.tab_off + ts) * kInnerStates + 4 * (lane & 15) + (lane >> 4)];
     const double e = (double)cj + (double)tj + Kb;
     const double wj = cj < __builtin_inff() ? exp2(-bb * e - lz2) : 0.0;
@@ -1023,7 +1028,7 @@ __global__ void __launch_bounds__(kBlock) sample_kernel(Views v, const float* be
       const uint64_t hi = ((local << I.L) | (uint64_t)ls) << I.no | (uint64_t)os;
       mout[id] = (hi << I.B) | (uint64_t)js;
     }
-    __builtin_amdgcn_wave_barrier();  // myq / myw / myc are rewritten by the next sample
+    __builtin_amdgcn_wave_barrier();  // myw / myc are rewritten by the next sample
   }
 }
 
