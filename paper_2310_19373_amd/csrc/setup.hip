@@ -3,7 +3,7 @@
 // plan_kernel    : bit split of every instance, work-unit / table / slot offsets,
 //                  queue and threshold reset (written by a kernel, so that a
 //                  captured graph replays it without memset nodes).
-// prep_inst      : symmetric copy of Q (the qua/lin split of Sec. 3: off-diagonal
+// prep_inst      : work unit -> instance map, symmetric copy of Q (the qua/lin split of Sec. 3: off-diagonal
 //                  S = triu(Q,1) + triu(Q,1)^T, diagonal d = diag(Q)), sum |Q|,
 //                  validation, and the inner-bit energies E_I(j).
 // prep_walk      : one launch of three independent roles per instance: the
@@ -103,9 +103,6 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
       I.tab_off = cs;
       I.slot_off = csl;
       I.slot_cap = min<int64_t>(s.units, pp.waves);
-      if (v.umap)
-        for (int64_t u = 0; u < s.units; ++u)
-          if (cu + u < v.umap_cap) v.umap[cu + u] = (uint32_t)b;
       cu += s.units;
       cs += s.steps;
       csl += I.slot_cap;
@@ -148,6 +145,13 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
   __shared__ int red_bad[256], red_frac[256];
   const int b = blockIdx.x, tid = threadIdx.x;
   Inst* I = &v.inst[b];
+  // work unit -> instance map (for every instance with units, whatever its
+  // status: the walks look the instance up before they check it)
+  if (v.umap) {
+    const int64_t ub = I->unit_begin, nu = I->units;
+    for (int64_t u = tid; u < nu; u += blockDim.x)
+      if (ub + u < v.umap_cap) v.umap[ub + u] = (uint32_t)b;
+  }
   if (I->status != 0) return;
   const int n = I->n, nmax = v.nmax, B = I->B;
   const Qin* Q = q + (int64_t)b * stride;
