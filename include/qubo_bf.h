@@ -122,7 +122,7 @@ size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits);
  * lowest states among the masks whose top p_bits bits (p = mask >> (n - p_bits))
  * lie in [p_begin, p_end) -- the fixed-prefix sub-walks of Sec. 3.1, each a
  * contiguous block of masks.  Arguments, outputs and status as qubo_bf_solve;
- * the result is exact (and, for float32 Q, certified) for that range, so the
+ * the result is exact (and, for float Q, certified) for that range, so the
  * k lowest of the union of the results of disjoint ranges (qubo_bf_merge_topk)
  * is the result of qubo_bf_solve.
  *   p_bits   1 .. min(20, n - 12)
