@@ -5,8 +5,8 @@ The public functions load the HIP library on first use; importing the package
 """
 __version__ = "0.1.0"
 
-_API = ("solve", "solve_batched", "solve_range", "merge_topk", "logz", "LogZ", "logz_moments", "marginals", "logz_sample",
-        "masks_to_bits", "QuboError", "UncertainError")
+_API = ("solve", "solve_batched", "solve_range", "merge_topk", "solve_resumable", "logz", "LogZ", "logz_moments",
+        "marginals", "logz_sample", "masks_to_bits", "QuboError", "UncertainError")
 
 
 def __getattr__(name):

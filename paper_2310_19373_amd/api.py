@@ -2,6 +2,8 @@
 every computation runs in the HIP library.
 
 * ``solve(Q, k)``                   k lowest states of one QUBO
+* ``solve_range`` / ``merge_topk``  one prefix range of a solve / merge of such results
+* ``solve_resumable``               a solve in checkpointed prefix-range pieces
 * ``solve_batched(Qpad, ns, k)``    k lowest states of many QUBOs, one launch sequence
 * ``BatchedSolver``                 the same with persistent buffers and optional
                                     HIP-graph capture/replay
@@ -171,6 +173,50 @@ def merge_topk(results, k: int):
         _lib.check(_lib.lib().qubo_bf_merge_topk(en.shape[0], en.shape[1], en.data_ptr(), mk.data_ptr(), dt, k,
                                                  out_e.data_ptr(), out_m.data_ptr(), _stream(dev)))
     return out_e, out_m
+
+
+def solve_resumable(Q, k: int, p_bits: int, checkpoint: str, *, max_ranges: int | None = None):
+    """solve(Q, k) in 2^p_bits prefix-range pieces (solve_range), for long
+    enumerations: after each piece the merged result of the finished pieces
+    and the next prefix are written atomically to ``checkpoint`` (an .npz
+    file), and a later call with the same Q, k and p_bits resumes from it.
+
+    max_ranges bounds the pieces done by this call (None: all that remain).
+    Returns (energies, masks, done, total) with the k lowest so far and the
+    number of finished pieces; done == total means the result is final.
+    """
+    import hashlib
+    import os
+
+    Qd = _as_device(Q)
+    if Qd.ndim != 2 or Qd.shape[0] != Qd.shape[1]:
+        raise ValueError("Q must be square")
+    _check_upper(Qd)
+    n = Qd.shape[0]
+    total = 1 << p_bits
+    key = hashlib.sha256(Qd.cpu().numpy().tobytes()).hexdigest()
+    meta = np.array([n, k, p_bits, _qdtype(Qd)], dtype=np.int64)
+    dev = Qd.device
+    done, best = 0, None
+    if os.path.exists(checkpoint):
+        with np.load(checkpoint, allow_pickle=False) as z:
+            if str(z["q_sha256"]) != key or not np.array_equal(z["meta"], meta):
+                raise ValueError(f"{checkpoint} belongs to another instance, k or p_bits")
+            done = int(z["done"])
+            if done:
+                best = (torch.from_numpy(z["energies"]).to(dev), torch.from_numpy(z["masks"]).to(dev))
+    stop = total if max_ranges is None else min(total, done + max_ranges)
+    while done < stop:
+        part = solve_range(Qd, k, p_bits, done, done + 1, check_lower=False)
+        best = part if best is None else merge_topk([best, part], k)
+        done += 1
+        tmp = checkpoint + ".tmp.npz"
+        np.savez(tmp, q_sha256=np.array(key), meta=meta, done=np.array(done), energies=best[0].cpu().numpy(),
+                 masks=best[1].cpu().numpy())
+        os.replace(tmp, checkpoint)
+    if best is None:
+        raise ValueError("no piece finished yet (max_ranges=0)")
+    return best[0], best[1], done, total
 
 
 class BatchedSolver:

@@ -85,3 +85,23 @@ def test_seeded_ranges_against_oracle(gpu_lib, dtype, k, lo, hi):
     E, M = oracle.topk(Q, k, lo=lo << (n - pb), hi=hi << (n - pb))
     assert _u64(_np(m)) == _u64(M)
     assert np.array_equal(_np(e), E)
+
+
+def test_resumable_solve_checkpoints_and_resumes(gpu_lib, tmp_path):
+    import torch
+
+    n, k, pb = 26, 8, 3
+    Q = inputs.random_f32(n, 520)
+    ck = str(tmp_path / "state.npz")
+    e, m, done, total = api.solve_resumable(Q, k, pb, ck, max_ranges=3)
+    assert (done, total) == (3, 8)
+    E3, M3 = oracle.topk(Q, k, lo=0, hi=3 << (n - pb))
+    assert _u64(_np(m)) == _u64(M3) and np.array_equal(_np(e), E3)
+    e, m, done, _ = api.solve_resumable(Q, k, pb, ck, max_ranges=2)  # resumes at piece 3
+    assert done == 5
+    e, m, done, _ = api.solve_resumable(Q, k, pb, ck)
+    assert done == 8
+    fe, fm = api.solve(Q, k)
+    assert torch.equal(e, fe) and torch.equal(m, fm)
+    with pytest.raises(ValueError):
+        api.solve_resumable(inputs.random_f32(n, 521), k, pb, ck)  # another instance's checkpoint
