@@ -128,3 +128,21 @@ def test_sample_frequencies_match_probabilities(gpu_lib):
     cnt = np.bincount(m.cpu().numpy(), minlength=1 << n)
     sd = np.sqrt(N * p * (1 - p)) + 1.0
     assert np.all(np.abs(cnt - N * p) <= 5 * sd)
+
+
+def test_sample_n32_diagonal_marginals(gpu_lib):
+    # n = 32 (4096 work units per instance): for diagonal Q the bits are
+    # independent with P(x_i = 1) = 1 / (1 + exp(beta Q_ii)); 20000 samples'
+    # bit frequencies must lie within 5 sigma of it
+    n, beta, N = 32, 0.8, 20000
+    d = np.linspace(-2.0, 2.0, n).astype(np.float32)
+    Q = np.diag(d)
+    rng = np.random.default_rng(981)
+    m, lz = api.logz_sample(Q, beta, rng.random(N))
+    m = m.cpu().numpy().astype(np.uint64)
+    assert np.all(m < (np.uint64(1) << np.uint64(n)))
+    bits = ((m[:, None] >> np.arange(n, dtype=np.uint64)) & np.uint64(1)).astype(np.float64)
+    p = 1.0 / (1.0 + np.exp(beta * d.astype(np.float64)))
+    sd = np.sqrt(p * (1 - p) / N)
+    assert np.all(np.abs(bits.mean(axis=0) - p) <= 5 * sd + 1e-12)
+    assert abs(float(lz) - float(np.sum(np.log1p(np.exp(-beta * d.astype(np.float64)))))) <= 1e-5
