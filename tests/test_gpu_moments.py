@@ -74,3 +74,14 @@ def test_moments_batched_padding(gpu_lib):
         assert _rel(M[b, :n, :n], Mref) <= 1e-4, b
         assert np.all(M[b, n:, :] == 0) and np.all(M[b, :, n:] == 0), b
         assert abs(float(mean[b]) - mref) <= 1e-4 * max(1.0, abs(mref)), b
+
+
+def test_moments_n32_diagonal_closed_form(gpu_lib):
+    # n = 32: independent bits, E[x_i] = p_i, E[x_i x_j] = p_i p_j, E[f] = sum d_i p_i
+    n, beta = 32, 1.1
+    d = np.linspace(-1.5, 2.5, n).astype(np.float32)
+    lz, M, mean = api.logz_moments(np.diag(d), beta)
+    p = 1.0 / (1.0 + np.exp(beta * d.astype(np.float64)))
+    ref = np.triu(np.outer(p, p), 1) + np.diag(p)
+    assert _rel(M.cpu().numpy(), ref) <= 1e-4
+    assert abs(float(mean) - float(d.astype(np.float64) @ p)) <= 1e-4 * max(1.0, abs(float(d @ p)))
