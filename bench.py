@@ -9,8 +9,9 @@ walk, merge, float64 rescoring and certificate) with Q resident in HBM.
 
 Prints one JSON line: value = 2^40 * K / elapsed seconds, plus the roofline of
 the dominant kernel (the walk) from HIP events recorded around each of its
-launches on the call's stream, and the CPU oracle timed on a sample of the
-same workload.  Secondary workloads (batched, log-partition) are reported under
+launches on the call's stream, the CPU oracle timed on a sample of the
+same workload, and beside it the paper's own Gray-code method on the host
+cores (same sample scheme).  Secondary workloads (batched, log-partition) are reported under
 "extra" when --extra is given.
 """
 from __future__ import annotations
@@ -85,6 +86,27 @@ def cpu_baseline(Q, n, k):
     return {"value": states / dt, "unit": "states/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"{count} random prefix ranges of 2^22 masks (2^30 of the 2^40 states), "
                       f"natural-order float64 evaluation, {dt:.1f} s"}
+
+
+def cpu_paper_method(Q, n):
+    """The paper's own method on the host: the Gray-code walk of Algorithm 1
+    with the Sec. 3.1 prefix split, float64, O(n) per state, all host cores,
+    timed on 256 random 16-bit prefixes of the same instance (2^24 states
+    each).  Context beside the oracle baseline, not the target."""
+    from oracle import gray_cpu
+
+    m = 16
+    rng = np.random.default_rng(124)
+    prefixes = rng.choice(1 << m, 256, replace=False)
+    gray_cpu.minimum(Q, m, prefixes[:8])  # load the library, touch the pages
+    t0 = time.perf_counter()
+    gray_cpu.minimum(Q, m, prefixes)
+    dt = time.perf_counter() - t0
+    states = len(prefixes) * (1 << (n - m))
+    return {"value": states / dt, "unit": "states/s", "cores": gray_cpu.max_threads(),
+            "kind": "paper's method (Gray-code walk, Algorithm 1 + Sec. 3.1 prefix split, float64)",
+            "sample": f"{len(prefixes)} random prefixes of 16 bits, 2^{n - m} states each "
+                      f"(2^{int(np.log2(states))} of the 2^40 states), minimum only, {dt:.1f} s"}
 
 
 def _time(fn, reps):
@@ -408,6 +430,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, n, k)
+        out["cpu_paper_method"] = cpu_paper_method(Q, n)
     if args.extra:
         out["extra"] = {
             "single_n20_f32": extra_single(dev, "n=20 float32 N(0,1) (seed 0), k=8", inputs.single_n20_f32(), 8,
