@@ -28,10 +28,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU lane-operations per enumerated state of the block-table walk:
-# one table addition (v_add_f32 with a DPP row broadcast) plus half of a
-# three-input minimum (v_min3_f32 folds two states).
+# Algorithmic VALU lane-operations per enumerated state of the block-table walk.
+# float32 screen (and the int32 walk): one table addition (v_add_f32 with a DPP
+# row broadcast) plus half of a three-input minimum (v_min3_f32 folds two
+# states).  Half-precision screen (the float32 default): per block of 64 states
+# 32 v_pk_add_f16 (two states each) for C' + Tb, 28 v_pk_min_f16 for the
+# minimum over b, 4 v_pk_add_f16 for + Ta, 3 v_pk_min_f16 and 1 v_min_f16 for
+# the minimum over a: 68 / 64.
 ALG_OPS_PER_STATE = 1.5
+HALF_OPS_PER_STATE = 68 / 64
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 non-packed VALU lane-ops/s.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
@@ -120,11 +125,19 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
+def float_ops_per_state():
+    """Lane-ops per state of the float32 walk as the library is tuned now."""
+    from paper_2310_19373_amd import _lib
+
+    return HALF_OPS_PER_STATE if _lib.get_tuning(_lib.TUNE_HALF_SCREEN) > 0 else ALG_OPS_PER_STATE
+
+
 def extra_single(dev, name, Q, k, dt, reps, ops_per_state=ALG_OPS_PER_STATE):
     """One full qubo_bf_solve per call on another configuration; states/s of
     the call and the walk kernel's VALU roofline fraction (ops_per_state
-    lane-ops per state: 1.5 for the float32 / int32 walks, 3 for the float64
-    walk; HIP events around the walk launch)."""
+    lane-ops per state: 68/64 for the float32 walk's half screen, 1.5 for its
+    float32 screen and the int32 walk, 3 for the float64 walk; HIP events
+    around the walk launch)."""
     import torch
 
     from paper_2310_19373_amd import _lib
@@ -406,7 +419,8 @@ def main():
     states = float(1 << n)
     value = states * args.steps / elapsed
     walk_avg_s = walk_ms / 1e3 / max(walk_n, 1)
-    achieved = states * ALG_OPS_PER_STATE / walk_avg_s / 1e12
+    ops = float_ops_per_state()
+    achieved = states * ops / walk_avg_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
     out = {
         "metric": "QUBO states evaluated/sec at n=40",
@@ -425,8 +439,9 @@ def main():
                                "2^40 states per step, float64 rescoring of the top candidates"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU lane-op/s",
                      "frac": achieved / peak, "traffic": committed_traffic(),
-                     "kernel": "walk_topk", "kernel_ms": walk_avg_s * 1e3,
-                     "ops_per_state": ALG_OPS_PER_STATE},
+                     "kernel": "walk_topk_h16_kernel" if ops == HALF_OPS_PER_STATE else "walk_topk_kernel",
+                     "kernel_ms": walk_avg_s * 1e3,
+                     "ops_per_state": ops},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, n, k)
@@ -434,7 +449,7 @@ def main():
     if args.extra:
         out["extra"] = {
             "single_n20_f32": extra_single(dev, "n=20 float32 N(0,1) (seed 0), k=8", inputs.single_n20_f32(), 8,
-                                           _lib.QUBO_F32, 50),
+                                           _lib.QUBO_F32, 50, ops_per_state=float_ops_per_state()),
             "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
                                            inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10),
             "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64, k=16, float64 walk",

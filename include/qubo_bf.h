@@ -238,6 +238,11 @@ const char* qubo_version(void);
  *   QUBO_TUNE_SEED_SWEEPS         descent passes of the per-instance threshold
  *                                 seed before a top-k walk; -1: no seeding
  *                                 (speed only: results are identical)
+ *   QUBO_TUNE_HALF_SCREEN         float32 top-k walks: 1 screens each block of
+ *                                 64 states in packed float16 (with a margin
+ *                                 that keeps every block the float32 screen
+ *                                 passes); -1: float32 screen (results are
+ *                                 identical: passing blocks are replayed exactly)
  * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)
  * set the initial values.  Returns QUBO_OK or QUBO_ERR_INVALID_ARG.
  */
@@ -251,7 +256,8 @@ enum {
   QUBO_TUNE_CHUNK_BATCHED = 7,
   QUBO_TUNE_DYNAMIC_QUEUE = 8,
   QUBO_TUNE_LOGZ_FACTORED = 9,
-  QUBO_TUNE_SEED_SWEEPS = 10
+  QUBO_TUNE_SEED_SWEEPS = 10,
+  QUBO_TUNE_HALF_SCREEN = 11
 };
 int qubo_bf_set_tuning(int knob, int value);
 int qubo_bf_get_tuning(int knob);

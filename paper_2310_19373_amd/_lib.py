@@ -36,6 +36,7 @@ TUNE_CHUNK_BATCHED = 7
 TUNE_DYNAMIC_QUEUE = 8
 TUNE_LOGZ_FACTORED = 9
 TUNE_SEED_SWEEPS = 10
+TUNE_HALF_SCREEN = 11
 
 # Every symbol include/qubo_bf.h declares: name -> (restype, argtypes)
 _vp, _sz, _i, _i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64

@@ -50,6 +50,7 @@ struct Tuning {
   int dyn = 1;
   int logz_factored = 1;
   int seed_sweeps = 2;
+  int half_screen = 1;
 };
 
 int env_int(const char* name, int dflt) {
@@ -71,6 +72,7 @@ Tuning& tuning() {
     d.dyn = env_int("QUBO_BF_DYNAMIC_QUEUE", d.dyn);
     d.logz_factored = env_int("QUBO_BF_LOGZ_FACTORED", d.logz_factored);
     d.seed_sweeps = env_int("QUBO_BF_SEED_SWEEPS", d.seed_sweeps);
+    d.half_screen = env_int("QUBO_BF_HALF_SCREEN", d.half_screen);
     return d;
   }();
   return t;
@@ -240,6 +242,7 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.batch = batch;
   v.nmax = nmax;
   v.dyn = tuning().dyn != 0;
+  v.h16 = 0;
   return v;
 }
 
@@ -319,9 +322,13 @@ PlanParams with_dt(PlanParams pp, qubo_dtype dt) {
 }
 
 // Enqueue plan -> prep -> tables -> walk -> finalize for a top-k call.
-int run_topk(const Views& v, const void* Q, int64_t ldq, int64_t stride, const int32_t* ns, int n_single,
+int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const int32_t* ns, int n_single,
              int dt, int k, PlanParams pp, int64_t units_hint, int64_t steps_hint, void* energies,
              uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
+  Views v = v0;
+  // float32 walks screen blocks in packed float16 (the step tables then hold
+  // HalfRow rows, 64 of the 256 bytes a float32 row takes)
+  v.h16 = (dt == kDtF32 && pp.inner == kInner && tuning().half_screen > 0) ? 1 : 0;
   int waves = grid_waves();
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;
@@ -366,6 +373,7 @@ int qubo_bf_set_tuning(int knob, int value) {
     case QUBO_TUNE_DYNAMIC_QUEUE: t.dyn = value > 0 ? 1 : (value < 0 ? 0 : d.dyn); break;
     case QUBO_TUNE_LOGZ_FACTORED: t.logz_factored = value > 0 ? 1 : (value < 0 ? 0 : d.logz_factored); break;
     case QUBO_TUNE_SEED_SWEEPS: t.seed_sweeps = value > 0 ? clampi(value, 1, 256) : (value < 0 ? 0 : d.seed_sweeps); break;
+    case QUBO_TUNE_HALF_SCREEN: t.half_screen = value > 0 ? 1 : (value < 0 ? 0 : d.half_screen); break;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
   return QUBO_OK;
@@ -384,6 +392,7 @@ int qubo_bf_get_tuning(int knob) {
     case QUBO_TUNE_DYNAMIC_QUEUE: return t.dyn;
     case QUBO_TUNE_LOGZ_FACTORED: return t.logz_factored;
     case QUBO_TUNE_SEED_SWEEPS: return t.seed_sweeps;
+    case QUBO_TUNE_HALF_SCREEN: return t.half_screen;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }
 }

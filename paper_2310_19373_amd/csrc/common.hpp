@@ -82,6 +82,11 @@ struct Inst {
   double big;               // threshold that no state exceeds
   double eps;               // bound on |f32 walk value - exact value| (float path)
   double sign;              // +1, or -1 when the walk runs on -Q
+  // half-precision screen of the float32 walk: table values are scaled by
+  // hscale (a power of two putting the inner bound R_I in [2^12, 2^13)) and
+  // the screen's threshold is raised by hmargin (scaled units)
+  double hscale;
+  double hmargin;
 };
 
 // Work-queue segments: the unit range is cut into kXcds contiguous pieces, one
@@ -108,6 +113,19 @@ struct Header {
 };
 
 // Per-step uniform data of the outer walk.
+// One outer step of the float32 walk's half-precision screen (64 bytes, read
+// with scalar loads): the inner 6 bits j = b | a << 3 split into 3 + 3, and
+// T'(j) = Tb(b) + Ta(a) (T' is linear in the inner bits).  tb[b] holds Tb(b)
+// in both halves, ta[a] holds (Ta(a), Ta(a + 4)), all float16 of the scaled
+// values; tau = hscale * E_O(g(t)) - hmargin.
+struct HalfRow {
+  uint32_t tb[8];
+  uint32_t ta[4];
+  double tau;
+  uint32_t pad[2];
+};
+static_assert(sizeof(HalfRow) == 64, "HalfRow is one 64-byte scalar load");
+
 struct StepRec {
   double eo;      // E_O(g(t))
   double h[6];    // H_u(g(t)) = sum_{v in O} S_uv x_v, u < 6

@@ -33,6 +33,7 @@ struct Views {
   int64_t umap_cap;
   int batch, nmax;
   int dyn;         // 1: atomic work queue, 0: static round-robin of chunks
+  int h16;         // float32 top-k walk: 1 = half-precision screen (tab holds HalfRow rows)
 };
 
 struct PlanParams {

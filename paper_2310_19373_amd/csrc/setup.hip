@@ -199,6 +199,8 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
   if (tid == 0) {
     const double sa = red_a[0];
     I->sumabs = sa;
+    I->hscale = 1.0;
+    I->hmargin = 0.0;
     if constexpr (std::is_same_v<E, int32_t>) {
       I->big = sa + 1.0;
       I->eps = 0.0;
@@ -229,6 +231,23 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
       // so the walk is exact (eps = 0) and ties are resolved like the int path.
       if (!red_frac[0] && sa <= 16777216.0) I->eps = 0.0;
       if (red_bad[0]) I->status = kErrNonfinite;
+      // Half-precision screen.  Every screened value and partial sum (C',
+      // Tb, Ta, C' + Tb, C' + Tb + Ta) is a partial sum of the inner rows, so
+      // at most R_I in magnitude; scaled by hs = 2^s with R_I hs in
+      // [2^12, 2^13) it stays far inside float16 range.  Five float16
+      // roundings (relative 2^-11 each) and the float32 ones put the screened
+      // value within 5.01 * 2^-11 * R_I hs of hs times the float32 walk's;
+      // the threshold's float64 / float32 roundings add at most
+      // 2^-22 R_I hs + 2^-52 sum|Q| hs; float16 subnormals (or their flush)
+      // at most 5 * 2^-14.  hmargin covers all of it, so every block the
+      // float32 screen would pass also passes the half screen, and the
+      // float32 walk's error bound eps still holds.
+      if (red_r[0] > 0.0 && isfinite(red_r[0])) {
+        int e;
+        frexp(red_r[0], &e);  // R_I in [2^(e-1), 2^e)
+        I->hscale = ldexp(1.0, 13 - e);
+      }
+      I->hmargin = I->hscale * (0x1p-8 * red_r[0] + 0x1p-50 * sa) + 0x1p-10;
     }
   }
 }
@@ -502,6 +521,35 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
     for (int u = 0; u < 6; ++u) r->h[u] = (double)H[u];
     r->neo = (int32_t)(-eo);
     r->pad = 0;
+    if constexpr (std::is_same_v<E, float>) {
+      if (v.h16) {
+        // the half screen's row: Tb / Ta from the linear split of T'
+        const double hs = I->hscale;
+        HalfRow hr;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          double tb = 0, ta = 0;
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            if ((c >> u) & 1) {
+              tb += (double)H[u];
+              ta += (double)H[3 + u];
+            }
+          }
+          const uint32_t hb = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(tb * hs));
+          const uint32_t ha = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(ta * hs));
+          hr.tb[c] = hb | (hb << 16);
+          if (c < 4) hr.ta[c] = ha;
+          else hr.ta[c - 4] |= ha << 16;
+        }
+        hr.tau = (double)eo * hs - I->hmargin;
+        hr.pad[0] = hr.pad[1] = 0;
+        ((HalfRow*)v.tab)[s] = hr;
+      }
+    }
+  }
+  if constexpr (std::is_same_v<E, float>) {
+    if (v.h16) return;  // the half screen reads HalfRow rows only
   }
 #pragma unroll
   for (int u = 0; u < 6; ++u) hs[w][u][lane] = H[u];

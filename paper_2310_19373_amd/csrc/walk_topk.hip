@@ -259,7 +259,199 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   }
 }
 
-template <class E>
+// ---- float32 walk with the half-precision screen ----------------------------
+//
+// Same walk, same replay, same thresholds; only the per-step block screen
+// changes.  The inner index j = b | a << 3 splits 3 + 3 and T'(g(t); j) =
+// Tb(b) + Ta(a) (T' is linear in the inner bits), so one step reads a 64-byte
+// HalfRow with scalar loads and computes, in packed float16 on the scaled
+// values,
+//   m = min_a [ Ta(a) + min_b (C'(b | a << 3) + Tb(b)) ]
+// with C' paired as (a, a + 4) per register: 32 v_pk_add_f16 (two states
+// each), 28 + 3 + 1 v_pk_min_f16 / v_min_f16 and 4 v_pk_add_f16 for 64 states.
+// The float64 offset Dp is kept scaled by hscale (exact: a power of two), and
+// the block passes when m <= Dp - tau, tau = hscale E_O - hmargin.  hmargin
+// makes the half screen pass every block the float32 screen passes; the
+// replay recomputes passing blocks with exact keys.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(4))) uint32_t* half_words_t;
+
+__device__ __forceinline__ h2 as_h2(uint32_t x) { return __builtin_bit_cast(h2, x); }
+__device__ __forceinline__ h2 hmin2(h2 a, h2 b) { return __builtin_elementwise_min(a, b); }
+
+__device__ __forceinline__ float half_block_min(const HalfRow& r, const h2 (&C)[4][8]) {
+  h2 m[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    h2 s[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[c] = C[a][c] + as_h2(r.tb[c]);
+    s[0] = hmin2(s[0], s[1]);
+    s[2] = hmin2(s[2], s[3]);
+    s[4] = hmin2(s[4], s[5]);
+    s[6] = hmin2(s[6], s[7]);
+    s[0] = hmin2(s[0], s[2]);
+    s[4] = hmin2(s[4], s[6]);
+    m[a] = hmin2(s[0], s[4]) + as_h2(r.ta[a]);
+  }
+  m[0] = hmin2(m[0], m[1]);
+  m[2] = hmin2(m[2], m[3]);
+  m[0] = hmin2(m[0], m[2]);
+  const h2 f = hmin2(m[0], __builtin_shufflevector(m[0], m[0], 1, 0));
+  return (float)f.x;
+}
+
+// Waits for every scalar-memory / LDS result in flight (the row of the step
+// about to run); issued before the next row's loads so that wait never covers
+// them.
+__device__ __forceinline__ void wait_rows() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU& I, uint64_t local, double& lkey,
+                                              uint64_t& lmask, uint64_t& pub, double* myc, int lane) {
+  const bool valid = lane < (1 << I.L);
+  const uint64_t p = (local << I.L) | (uint64_t)lane;
+  const double hs = uniform_f64(gp((const Inst*)v.inst)[b].hscale);
+  const double his = 1.0 / hs;  // exact: hs is a power of two
+
+  float C[64];
+  const double EP = lane_init<float, 64>(v, b, I, local, valid, myc, lane, C);
+  h2 C16[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      C16[a][c] = h2{(_Float16)((double)C[c | a << 3] * hs), (_Float16)((double)C[c | (a + 4) << 3] * hs)};
+
+  const double g0 = load_gthr(v, b);
+  if (enc_key(g0) < pub) pub = enc_key(g0);
+  double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
+  double Dp = (thr - EP) * hs;  // the float32 walk's Dp, scaled
+  const uint32_t steps = 1u << I.no;
+  // the rows through the constant address space: scalar loads
+  const half_words_t rows = (half_words_t)((const HalfRow*)v.tab + I.tab_off);
+  const double c0 = I.no > 0 ? myc[lane] * hs : 0.0;
+  const double c1 = I.no > 1 ? myc[kWave + lane] * hs : 0.0;
+  const double c2 = I.no > 2 ? myc[2 * kWave + lane] * hs : 0.0;
+
+  auto row = [&](uint32_t t) -> HalfRow {
+    const half_words_t w = rows + (size_t)(t < steps ? t : steps - 1) * (sizeof(HalfRow) / 4);
+    HalfRow r;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r.tb[c] = w[c];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) r.ta[a] = w[8 + a];
+    r.tau = __builtin_bit_cast(double, (uint64_t)w[12] | ((uint64_t)w[13] << 32));
+    return r;
+  };
+  auto retune = [&](double nthr) {
+    Dp += (nthr - thr) * hs;
+    thr = nthr;
+  };
+  auto body = [&](uint32_t t, const HalfRow& r) {
+    const float m = half_block_min(r, C16);
+    const bool hit = m <= (float)(Dp - r.tau);
+    if (__builtin_expect(ballot(hit) != 0, 0)) {
+      double nthr = thr;
+      const double eo = uniform_f64(gp((const StepRec*)v.rec)[I.tab_off + t].eo);
+      const double KE = thr - Dp * his + eo;
+      replay<float>(v, b, I, t, p, valid, KE, nthr, lkey, lmask, pub, myc, lane);
+      retune(nthr);
+    }
+  };
+  auto flip_on = [&](double c) { Dp -= c; };
+  auto flip_off = [&](double c) { Dp += c; };
+  auto flip_sign = [&](bool off, double c) { Dp = __builtin_fma(off ? 1.0 : -1.0, c, Dp); };
+
+  if (steps < 16) {
+    HalfRow cur = row(0);
+    for (uint32_t t = 0; t < steps; ++t) {
+      if (t) {
+        const int l = __builtin_ctz(t);
+        flip_sign((t >> (l + 1)) & 1, myc[l * kWave + lane] * hs);
+      }
+      wait_rows();
+      const HalfRow nxt = row(t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      body(t, cur);
+      cur = nxt;
+    }
+    return;
+  }
+  // steps >= 16: unrolled by 8 as the float32 walk.  At the top of each step
+  // the row of that step is waited for and the next row's loads are issued;
+  // two rows are live (ev / od).  The cross field of the group's last flip
+  // (bit 3 + CTZ(q + 1)) is read from LDS one step early, before a row load,
+  // so the wait that covers it is the next step's row wait.
+  HalfRow ev = row(0), od;
+  wait_rows();
+  od = row(1);
+  __builtin_amdgcn_sched_barrier(0);
+  body(0, ev);
+  const uint32_t groups = steps >> 3;
+  for (uint32_t q = 0;; ++q) {
+    const uint32_t t = 8 * q;
+    wait_rows();
+    ev = row(t + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_on(c0);
+    body(t + 1, od);
+    wait_rows();
+    od = row(t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_on(c1);
+    body(t + 2, ev);
+    wait_rows();
+    ev = row(t + 4);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_off(c0);
+    body(t + 3, od);
+    wait_rows();
+    od = row(t + 5);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_sign(q & 1, c2);
+    body(t + 4, ev);
+    wait_rows();
+    ev = row(t + 6);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_on(c0);
+    body(t + 5, od);
+    wait_rows();
+    od = row(t + 7);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_off(c1);
+    body(t + 6, ev);
+    if (q + 1 == groups) {
+      wait_rows();
+      flip_off(c0);
+      body(t + 7, od);
+      break;
+    }
+    wait_rows();
+    const uint32_t t8 = t + 8;
+    const int l8 = __builtin_ctz(t8);
+    const double cl = myc[l8 * kWave + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    ev = row(t8);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_off(c0);
+    body(t + 7, od);
+    wait_rows();
+    od = row(t8 + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_sign((t8 >> (l8 + 1)) & 1, cl * hs);
+    body(t8, ev);
+    if (((q + 1) & 7) == 0) {
+      const double g = load_gthr(v, b);
+      if (enc_key(g) < pub) pub = enc_key(g);
+      if (g < thr) retune(g);
+    }
+  }
+}
+
+template <class E, bool kHalf>
 __device__ __forceinline__ void walk_topk_body(const Views& v) {
   using W = typename Ar<E>::W;
   __shared__ W ctab[kWavesPerBlock][kWaveRows * kWave];
@@ -282,8 +474,11 @@ __device__ __forceinline__ void walk_topk_body(const Views& v) {
       cur = b;
     }
     const InstU I = load_inst(v, b);
-    if (I.status == 0)
-      walk_unit<E>(v, b, I, u - (uint64_t)I.unit_begin + (uint64_t)I.local_off, lkey, lmask, pub, myc, lane);
+    if (I.status == 0) {
+      const uint64_t local = u - (uint64_t)I.unit_begin + (uint64_t)I.local_off;
+      if constexpr (kHalf) walk_unit_h16(v, b, I, local, lkey, lmask, pub, myc, lane);
+      else walk_unit<E>(v, b, I, local, lkey, lmask, pub, myc, lane);
+    }
   }
   if (cur >= 0) flush(v, cur, lkey, lmask, lane);
 }
@@ -292,10 +487,13 @@ __device__ __forceinline__ void walk_topk_body(const Views& v) {
 // walk (its 32-entry table and broadcast temporaries take 2x the VGPRs).
 template <class E>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_kernel(Views v) {
-  walk_topk_body<E>(v);
+  walk_topk_body<E, false>(v);
 }
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_topk_f64_kernel(Views v) {
-  walk_topk_body<double>(v);
+  walk_topk_body<double, false>(v);
+}
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_h16_kernel(Views v) {
+  walk_topk_body<float, true>(v);
 }
 
 }  // namespace
@@ -306,6 +504,8 @@ hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s) {
     hipLaunchKernelGGL(walk_topk_kernel<int32_t>, dim3(blocks), dim3(kBlock), 0, s, v);
   else if (dt_wide(dt))
     hipLaunchKernelGGL(walk_topk_f64_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
+  else if (v.h16)
+    hipLaunchKernelGGL(walk_topk_h16_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
   else
     hipLaunchKernelGGL(walk_topk_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, v);
   return hipGetLastError();

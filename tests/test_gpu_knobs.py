@@ -1,9 +1,9 @@
 """Speed-only tuning knobs leave every output bit-identical.
 
 Work distribution (dynamic XCD-segmented queue vs static round-robin, chunk
-caps), the threshold seed (on, off, more descent passes) and the launch shape
-(outer bits, waves per CU) change which wave walks which states and when,
-never the results.  Each case compares against the default setting and, on
+caps), the threshold seed (on, off, more descent passes), the launch shape
+(outer bits, waves per CU) and the float32 walk's block screen (packed float16
+or float32) change which wave walks which states and when, never the results.  Each case compares against the default setting and, on
 small sizes, against the oracle.
 """
 import numpy as np
@@ -24,10 +24,12 @@ SETTINGS = [
     {"chunk_single": 16, "chunk_batched": 32},
     {"waves_per_cu": 4},
     {"single_outer": 8, "batched_outer": 6},
+    {"half": -1},
 ]
 KNOB = {"dyn": _lib.TUNE_DYNAMIC_QUEUE, "seed": _lib.TUNE_SEED_SWEEPS, "chunk_single": _lib.TUNE_CHUNK_SINGLE,
         "chunk_batched": _lib.TUNE_CHUNK_BATCHED, "waves_per_cu": _lib.TUNE_WAVES_PER_CU,
-        "single_outer": _lib.TUNE_SINGLE_OUTER_BITS, "batched_outer": _lib.TUNE_BATCHED_OUTER_BITS}
+        "single_outer": _lib.TUNE_SINGLE_OUTER_BITS, "batched_outer": _lib.TUNE_BATCHED_OUTER_BITS,
+        "half": _lib.TUNE_HALF_SCREEN}
 
 
 class _knobs:
