@@ -32,11 +32,11 @@ sys.path.insert(0, ROOT)
 # float32 screen (and the int32 walk): one table addition (v_add_f32 with a DPP
 # row broadcast) plus half of a three-input minimum (v_min3_f32 folds two
 # states).  Half-precision screen (the float32 default): per block of 64 states
-# 32 v_pk_add_f16 (two states each) for C' + Tb, 28 v_pk_min_f16 for the
-# minimum over b, 4 v_pk_add_f16 for + Ta, 3 v_pk_min_f16 and 1 v_min_f16 for
-# the minimum over a: 68 / 64.
+# 32 v_pk_add_f16 (two states each) for C' + Tb, 30 v_pk_min_f16 for the
+# minimum over b, 2 v_pk_add_f16 for + Ta, 1 v_pk_min_f16 and 1 v_min_f16 for
+# the minimum over a: 66 / 64.
 ALG_OPS_PER_STATE = 1.5
-HALF_OPS_PER_STATE = 68 / 64
+HALF_OPS_PER_STATE = 66 / 64
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 non-packed VALU lane-ops/s.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 

@@ -114,15 +114,16 @@ struct Header {
 
 // Per-step uniform data of the outer walk.
 // One outer step of the float32 walk's half-precision screen (64 bytes, read
-// with scalar loads): the inner 6 bits j = b | a << 3 split into 3 + 3, and
-// T'(j) = Tb(b) + Ta(a) (T' is linear in the inner bits).  tb[b] holds Tb(b)
-// in both halves, ta[a] holds (Ta(a), Ta(a + 4)), all float16 of the scaled
-// values; tau = hscale * E_O(g(t)) - hmargin.
+// with scalar loads): the inner 6 bits j = b | a << 4 split into 4 + 2, and
+// T'(j) = Tb(b) + Ta(a) (T' is linear in the inner bits).  tb[k] holds
+// (Tb(2k), Tb(2k + 1)), ta[a] holds (Ta(a), Ta(a + 2)), all float16 of the
+// scaled values; tau = hscale * E_O(g(t)) - hmargin.
 struct HalfRow {
   uint32_t tb[8];
-  uint32_t ta[4];
+  uint32_t ta[2];
+  uint32_t pad0[2];
   double tau;
-  uint32_t pad[2];
+  uint32_t pad1[2];
 };
 static_assert(sizeof(HalfRow) == 64, "HalfRow is one 64-byte scalar load");
 

@@ -525,25 +525,23 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
       if (v.h16) {
         // the half screen's row: Tb / Ta from the linear split of T'
         const double hs = I->hscale;
+        auto h16 = [&](double x) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(x * hs)); };
         HalfRow hr;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          double tb = 0, ta = 0;
+        for (int k = 0; k < 8; ++k) {
+          double lo = 0, hi = 0;  // Tb(2k), Tb(2k + 1)
 #pragma unroll
-          for (int u = 0; u < 3; ++u) {
-            if ((c >> u) & 1) {
-              tb += (double)H[u];
-              ta += (double)H[3 + u];
-            }
+          for (int u = 1; u < 4; ++u) {
+            if (((2 * k) >> u) & 1) lo += (double)H[u];
           }
-          const uint32_t hb = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(tb * hs));
-          const uint32_t ha = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(ta * hs));
-          hr.tb[c] = hb | (hb << 16);
-          if (c < 4) hr.ta[c] = ha;
-          else hr.ta[c - 4] |= ha << 16;
+          hi = lo + (double)H[0];
+          hr.tb[k] = h16(lo) | (h16(hi) << 16);
         }
+        const double ta[4] = {0.0, (double)H[4], (double)H[5], (double)H[4] + (double)H[5]};
+        hr.ta[0] = h16(ta[0]) | (h16(ta[2]) << 16);
+        hr.ta[1] = h16(ta[1]) | (h16(ta[3]) << 16);
+        hr.pad0[0] = hr.pad0[1] = hr.pad1[0] = hr.pad1[1] = 0;
         hr.tau = (double)eo * hs - I->hmargin;
-        hr.pad[0] = hr.pad[1] = 0;
         ((HalfRow*)v.tab)[s] = hr;
       }
     }

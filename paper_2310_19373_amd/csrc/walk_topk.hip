@@ -262,41 +262,41 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
 // ---- float32 walk with the half-precision screen ----------------------------
 //
 // Same walk, same replay, same thresholds; only the per-step block screen
-// changes.  The inner index j = b | a << 3 splits 3 + 3 and T'(g(t); j) =
+// changes.  The inner index j = b | a << 4 splits 4 + 2 and T'(g(t); j) =
 // Tb(b) + Ta(a) (T' is linear in the inner bits), so one step reads a 64-byte
 // HalfRow with scalar loads and computes, in packed float16 on the scaled
 // values,
-//   m = min_a [ Ta(a) + min_b (C'(b | a << 3) + Tb(b)) ]
-// with C' paired as (a, a + 4) per register: 32 v_pk_add_f16 (two states
-// each), 28 + 3 + 1 v_pk_min_f16 / v_min_f16 and 4 v_pk_add_f16 for 64 states.
-// The float64 offset Dp is kept scaled by hscale (exact: a power of two), and
-// the block passes when m <= Dp - tau, tau = hscale E_O - hmargin.  hmargin
-// makes the half screen pass every block the float32 screen passes; the
-// replay recomputes passing blocks with exact keys.
+//   m = min_a [ Ta(a) + min_b (C'(b | a << 4) + Tb(b)) ]
+// with C' paired as (a, a + 2) per register: 32 v_pk_add_f16 (two states
+// each, Tb(b) taken from either half of a scalar register by op_sel),
+// 30 v_pk_min_f16, 2 v_pk_add_f16 for + Ta and 2 minimums: 66 instructions
+// for 64 states.  The float64 offset Dp is kept scaled by hscale (exact: a
+// power of two), and the block passes when m <= Dp - tau, tau = hscale E_O -
+// hmargin.  hmargin makes the half screen pass every block the float32 screen
+// passes; the replay recomputes passing blocks with exact keys.
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(4))) uint32_t* half_words_t;
 
 __device__ __forceinline__ h2 as_h2(uint32_t x) { return __builtin_bit_cast(h2, x); }
 __device__ __forceinline__ h2 hmin2(h2 a, h2 b) { return __builtin_elementwise_min(a, b); }
 
-__device__ __forceinline__ float half_block_min(const HalfRow& r, const h2 (&C)[4][8]) {
-  h2 m[4];
+__device__ __forceinline__ float half_block_min(const HalfRow& r, const h2 (&C)[2][16]) {
+  h2 m[2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    h2 s[8];
+  for (int a = 0; a < 2; ++a) {
+    h2 s[16];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) s[c] = C[a][c] + as_h2(r.tb[c]);
-    s[0] = hmin2(s[0], s[1]);
-    s[2] = hmin2(s[2], s[3]);
-    s[4] = hmin2(s[4], s[5]);
-    s[6] = hmin2(s[6], s[7]);
-    s[0] = hmin2(s[0], s[2]);
-    s[4] = hmin2(s[4], s[6]);
-    m[a] = hmin2(s[0], s[4]) + as_h2(r.ta[a]);
+    for (int c = 0; c < 16; ++c) {
+      const h2 x = as_h2(r.tb[c >> 1]);
+      s[c] = C[a][c] + ((c & 1) ? __builtin_shufflevector(x, x, 1, 1) : __builtin_shufflevector(x, x, 0, 0));
+    }
+#pragma unroll
+    for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+      for (int c = 0; c < w; ++c) s[c] = hmin2(s[c], s[c + w]);
+    m[a] = s[0] + as_h2(r.ta[a]);
   }
   m[0] = hmin2(m[0], m[1]);
-  m[2] = hmin2(m[2], m[3]);
-  m[0] = hmin2(m[0], m[2]);
   const h2 f = hmin2(m[0], __builtin_shufflevector(m[0], m[0], 1, 0));
   return (float)f.x;
 }
@@ -318,12 +318,12 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
 
   float C[64];
   const double EP = lane_init<float, 64>(v, b, I, local, valid, myc, lane, C);
-  h2 C16[4][8];
+  h2 C16[2][16];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      C16[a][c] = h2{(_Float16)((double)C[c | a << 3] * hs), (_Float16)((double)C[c | (a + 4) << 3] * hs)};
+    for (int c = 0; c < 16; ++c)
+      C16[a][c] = h2{(_Float16)((double)C[c | a << 4] * hs), (_Float16)((double)C[c | (a + 2) << 4] * hs)};
 
   const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
@@ -341,8 +341,8 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
     HalfRow r;
 #pragma unroll
     for (int c = 0; c < 8; ++c) r.tb[c] = w[c];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) r.ta[a] = w[8 + a];
+    r.ta[0] = w[8];
+    r.ta[1] = w[9];
     r.tau = __builtin_bit_cast(double, (uint64_t)w[12] | ((uint64_t)w[13] << 32));
     return r;
   };
