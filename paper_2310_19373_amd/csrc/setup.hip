@@ -525,7 +525,7 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
       if (v.h16) {
         // the half screen's row: Tb / Ta from the linear split of T'
         const double hs = I->hscale;
-        auto h16 = [&](double x) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(x * hs)); };
+        auto h16 = [&](double x) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(x * hs)); };
         HalfRow hr;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {

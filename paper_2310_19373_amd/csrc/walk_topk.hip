@@ -318,12 +318,17 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
 
   float C[64];
   const double EP = lane_init<float, 64>(v, b, I, local, valid, myc, lane, C);
+  // C' * hs: an exact float32 scaling (|C' hs| < 2^13), then one rounding
+  int hexp;
+  frexp(hs, &hexp);
+  hexp -= 1;  // hs = 2^hexp
   h2 C16[2][16];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 16; ++c)
-      C16[a][c] = h2{(_Float16)((double)C[c | a << 4] * hs), (_Float16)((double)C[c | (a + 2) << 4] * hs)};
+      C16[a][c] = h2{(_Float16)__builtin_ldexpf(C[c | a << 4], hexp),
+                     (_Float16)__builtin_ldexpf(C[c | (a + 2) << 4], hexp)};
 
   const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
