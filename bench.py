@@ -433,10 +433,13 @@ def main():
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16+f64" if ops == HALF_OPS_PER_STATE else "f32",
         "data": "synthetic",
         "config": {"workload": "single QUBO n=40, float32 N(0,1/n) + planted minimiser (seed 2), k=16, "
-                               "2^40 states per step, float64 rescoring of the top candidates"},
+                               "2^40 states per step, float64 rescoring of the top candidates",
+                   "screen": ("packed float16 block screen with a margin that keeps every block a float32 "
+                              "screen keeps; passing blocks replayed in float64; results identical to the "
+                              "float32 walk") if ops == HALF_OPS_PER_STATE else "float32 block screen"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T VALU lane-op/s",
                      "frac": achieved / peak, "traffic": committed_traffic(),
                      "kernel": "walk_topk_h16_kernel" if ops == HALF_OPS_PER_STATE else "walk_topk_kernel",
