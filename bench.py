@@ -9,7 +9,8 @@ walk, merge, float64 rescoring and certificate) with Q resident in HBM.
 
 Prints one JSON line: value = 2^40 * K / elapsed seconds, plus the roofline of
 the dominant kernel (the walk) from HIP events recorded around each of its
-launches on the call's stream, the CPU oracle timed on a sample of the
+launches on the call's stream, the same solve with the float32 block screen
+(its time, roofline and a bit-identity check against the timed outputs), the CPU oracle timed on a sample of the
 same workload, and beside it the paper's own Gray-code method on the host
 cores (same sample scheme).  Secondary workloads (batched, log-partition) are reported under
 "extra" when --extra is given.
@@ -446,6 +447,36 @@ def main():
                      "kernel_ms": walk_avg_s * 1e3,
                      "ops_per_state": ops},
     }
+    if ops == HALF_OPS_PER_STATE:
+        # the same solve with the float32 block screen, untimed in `value`:
+        # its own roofline and a check that the outputs are bit-identical
+        ref_e, ref_m = en.clone(), masks.clone()
+        saved = _lib.get_tuning(_lib.TUNE_HALF_SCREEN)
+        _lib.set_tuning(_lib.TUNE_HALF_SCREEN, -1)
+        try:
+            if L.qubo_bf_workspace_size(n, k, _lib.QUBO_F32) > ws_bytes:  # the plan may differ
+                ws_bytes = L.qubo_bf_workspace_size(n, k, _lib.QUBO_F32)
+                ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+            step()
+            torch.cuda.synchronize()
+            reps = max(1, min(args.steps, 5))
+            _lib.prof_enable(True)
+            _lib.prof_collect("walk_topk")
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            el32 = time.perf_counter() - t1
+            _lib.prof_enable(False)
+            w32_ms, w32_n = _lib.prof_collect("walk_topk")
+        finally:
+            _lib.set_tuning(_lib.TUNE_HALF_SCREEN, saved)
+        w32_s = w32_ms / 1e3 / max(w32_n, 1)
+        out["float32_screen"] = {
+            "value": states * reps / el32, "ms_per_step": el32 * 1e3 / reps, "steps": reps,
+            "kernel": "walk_topk_kernel", "kernel_ms": w32_s * 1e3, "ops_per_state": ALG_OPS_PER_STATE,
+            "frac": states * ALG_OPS_PER_STATE / w32_s / PEAK_LANE_OPS,
+            "identical": bool(torch.equal(ref_e, en) and torch.equal(ref_m, masks) and int(status.item()) == 0)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, n, k)
         out["cpu_paper_method"] = cpu_paper_method(Q, n)

@@ -224,7 +224,10 @@ const char* qubo_version(void);
  * workspace size, so query it again after a change.
  *   QUBO_TUNE_SINGLE_OUTER_BITS   max outer (Gray-walked) bits per work unit, single solve
  *   QUBO_TUNE_SINGLE_UNIT_BITS    prefix bits reserved for work units, single solve
- *                                 (upper bound; mid-size n reserves max(8, n - 18))
+ *                                 (upper bound, default 14; n <= 32 reserves
+ *                                 min(11, max(8, n - 18)), 12 in place of 11
+ *                                 and 13 in place of 14 for walks other than
+ *                                 the float32 half screen)
  *   QUBO_TUNE_BATCHED_OUTER_BITS  max outer bits per work unit, batched / logZ
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
  *   QUBO_TUNE_KPRIME              candidate list length override (float path;

@@ -41,7 +41,7 @@ constexpr int kMaxGridWaves = 8192;  // sizing bound of the persistent grid
 
 struct Tuning {
   int single_outer = 12;
-  int single_unit = 12;
+  int single_unit = 14;
   int batched_outer = 8;
   int waves_per_cu = 12;
   int kprime = 0;
@@ -246,14 +246,20 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   return v;
 }
 
-PlanParams single_params(int kp, int n) {
+PlanParams single_params(int kp, int n, int dt) {
   const Tuning& t = tuning();
   PlanParams pp{};
   pp.no_max = clampi(t.single_outer, 0, kMaxOuter);
   // unit bits reserved before outer bits are granted: the knob, lowered for
-  // mid-size n so that units keep a useful number of Gray steps (measured:
-  // n=24 -> 8, n=28 -> 10, n >= 30 -> 12)
-  const int want = n - 18 > 8 ? n - 18 : 8;
+  // mid-size n so that units keep a useful number of Gray steps, and raised
+  // from n = 33 so that a grid of ~3000 waves gets several units each.
+  // Measured with the float32 walk's half screen: n=24 -> 8, n=28 -> 10,
+  // n=30..32 -> 11, n=33..36 -> 14 (n=38 is flat; n=40 reaches 16 unit bits
+  // either way).  The walks with a costlier step (int32, float32 screen,
+  // float64) do best with one bit fewer: n=32 -> 12, n=34 -> 13.
+  const bool half = dt == kDtF32 && t.half_screen > 0;
+  const int mid_cap = half ? 11 : 12, big = half ? 14 : 13;
+  const int want = n >= 33 ? big : (n - 18 > mid_cap ? mid_cap : (n - 18 > 8 ? n - 18 : 8));
   pp.ub_min = clampi(t.single_unit < want ? t.single_unit : want, 0, 62);
   pp.inner = kInner;
   pp.kprime = kp;
@@ -432,7 +438,7 @@ size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt) {
   if (n < 1 || n > 63 || !valid_dtype(dt)) return 0;
   const bool exact = dt_exact(dt);
   if (check_k(k, exact) != QUBO_OK) return 0;
-  return make_layout(1, n, with_dt(single_params(kprime_for(k, exact), n), dt), 0, 0).total;
+  return make_layout(1, n, with_dt(single_params(kprime_for(k, exact), n, dt), dt), 0, 0).total;
 }
 
 int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
@@ -444,7 +450,7 @@ int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void*
   const bool exact = dt_exact(dt);
   if (int rc = check_k(k, exact)) return rc;
   const int kp = kprime_for(k, exact);
-  const PlanParams pp = with_dt(single_params(kp, n), dt);
+  const PlanParams pp = with_dt(single_params(kp, n, dt), dt);
   const Layout L = make_layout(1, n, pp, 0, 0);
   if (ws_bytes < L.total)
     return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
@@ -463,8 +469,8 @@ static int check_range(int n, int p_bits, int64_t p_begin, int64_t p_end) {
   return QUBO_OK;
 }
 
-static PlanParams range_params(int kp, int n, int p_bits, int64_t p_begin, int64_t p_end) {
-  PlanParams pp = single_params(kp, n);
+static PlanParams range_params(int kp, int n, int dt, int p_bits, int64_t p_begin, int64_t p_end) {
+  PlanParams pp = single_params(kp, n, dt);
   pp.range_bits = p_bits;
   pp.range_begin = p_begin;
   pp.range_end = p_end;
@@ -475,7 +481,7 @@ size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits) {
   if (n < 1 || n > 63 || !valid_dtype(dt) || p_bits < 1 || p_bits > 20 || p_bits > n - 12) return 0;
   const bool exact = dt_exact(dt);
   if (check_k(k, exact) != QUBO_OK) return 0;
-  return make_layout(1, n, with_dt(range_params(kprime_for(k, exact), n, p_bits, 0, 1), dt), 0, 0).total;
+  return make_layout(1, n, with_dt(range_params(kprime_for(k, exact), n, dt, p_bits, 0, 1), dt), 0, 0).total;
 }
 
 int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int p_bits, int64_t p_begin,
@@ -489,7 +495,7 @@ int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k,
   if (check_k(k, exact) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
   if (check_range(n, p_bits, p_begin, p_end) != QUBO_OK) return QUBO_ERR_INVALID_ARG;
   const int kp = kprime_for(k, exact);
-  const PlanParams pp = with_dt(range_params(kp, n, p_bits, p_begin, p_end), dt);
+  const PlanParams pp = with_dt(range_params(kp, n, dt, p_bits, p_begin, p_end), dt);
   const Layout L = make_layout(1, n, pp, 0, 0);
   if (ws_bytes < L.total) return fail(QUBO_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
   const Views v = make_views(ws, L, 1, n);
