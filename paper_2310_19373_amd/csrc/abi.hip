@@ -257,7 +257,7 @@ PlanParams single_params(int kp, int n, int dt) {
   // n=30..32 -> 11, n=33..36 -> 14 (n=38 is flat; n=40 reaches 16 unit bits
   // either way).  The walks with a costlier step (int32, float32 screen,
   // float64) do best with one bit fewer: n=32 -> 12, n=34 -> 13.
-  const bool half = dt == kDtF32 && t.half_screen > 0;
+  const bool half = (dt == kDtF32 || dt == kDtI32) && t.half_screen > 0;
   const int mid_cap = half ? 11 : 12, big = half ? 14 : 13;
   const int want = n >= 33 ? big : (n - 18 > mid_cap ? mid_cap : (n - 18 > 8 ? n - 18 : 8));
   pp.ub_min = clampi(t.single_unit < want ? t.single_unit : want, 0, 62);
@@ -333,8 +333,12 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
              uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
   Views v = v0;
   // float32 walks screen blocks in packed float16 (the step tables then hold
-  // HalfRow rows, 64 of the 256 bytes a float32 row takes)
-  v.h16 = (dt == kDtF32 && pp.inner == kInner && tuning().half_screen > 0) ? 1 : 0;
+  // HalfRow rows, 64 of the 256 bytes a float32 row takes); a single int32
+  // instance screens in exact int16 when its inner bound allows (in a batch
+  // the two row layouts would overlap between instances, so batches keep
+  // the int32 screen)
+  const bool half = tuning().half_screen > 0 && pp.inner == kInner;
+  v.h16 = (half && (dt == kDtF32 || (dt == kDtI32 && v.batch == 1))) ? 1 : 0;
   int waves = grid_waves();
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;

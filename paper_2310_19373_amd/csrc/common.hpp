@@ -42,6 +42,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxKPrime = 64;             // candidate list length (one entry per lane)
 constexpr int32_t kIntInvalid = 1 << 30;   // table sentinel of the int32 path
 constexpr int64_t kIntSumLimit = int64_t(1) << 28;  // int32 path: sum |Q| bound
+constexpr int32_t kInt16Limit = 32767;               // int16 screen: inner bound R_I
 // float64 walk: with sum |Q| <= 2^50 every intermediate of integer data (table
 // values, the running threshold offset, replay keys: at most 5 sum |Q| in
 // magnitude) is an integer below 2^53, so the walk is exact
@@ -82,9 +83,11 @@ struct Inst {
   double big;               // threshold that no state exceeds
   double eps;               // bound on |f32 walk value - exact value| (float path)
   double sign;              // +1, or -1 when the walk runs on -Q
-  // half-precision screen of the float32 walk: table values are scaled by
-  // hscale (a power of two putting the inner bound R_I in [2^12, 2^13)) and
-  // the screen's threshold is raised by hmargin (scaled units)
+  // half-width screen.  float32 walk: table values are scaled by hscale (a
+  // power of two putting the inner bound R_I in [2^12, 2^13)) and the
+  // screen's threshold is raised by hmargin (scaled units).  int32 walk:
+  // hscale = 1 when R_I <= 32767 (every screened value is an exact int16),
+  // else 0 (the instance keeps the int32 screen).
   double hscale;
   double hmargin;
 };
@@ -113,15 +116,17 @@ struct Header {
 };
 
 // Per-step uniform data of the outer walk.
-// One outer step of the float32 walk's half-precision screen (64 bytes, read
-// with scalar loads): the inner 6 bits j = b | a << 4 split into 4 + 2, and
-// T'(j) = Tb(b) + Ta(a) (T' is linear in the inner bits).  tb[k] holds
-// (Tb(2k), Tb(2k + 1)), ta[a] holds (Ta(a), Ta(a + 2)), all float16 of the
-// scaled values; tau = hscale * E_O(g(t)) - hmargin.
+// One outer step of a half-width screen (64 bytes, read with scalar loads):
+// the inner 6 bits j = b | a << 4 split into 4 + 2, and T'(j) = Tb(b) + Ta(a)
+// (T' is linear in the inner bits).  tb[k] holds (Tb(2k), Tb(2k + 1)), ta[a]
+// holds (Ta(a), Ta(a + 2)).  float32 walk: float16 of the scaled values, and
+// tau = hscale * E_O(g(t)) - hmargin; int32 walk: exact int16 values, and
+// neo = -E_O(g(t)).
 struct HalfRow {
   uint32_t tb[8];
   uint32_t ta[2];
-  uint32_t pad0[2];
+  int32_t neo;
+  uint32_t pad0;
   double tau;
   uint32_t pad1[2];
 };

@@ -205,6 +205,9 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
       I->big = sa + 1.0;
       I->eps = 0.0;
       if (sa > (double)kIntSumLimit) I->status = kErrRange;
+      // int16 screen: C', Tb, Ta and their sums are partial sums of the
+      // inner rows, exact int16 values when R_I <= 32767
+      I->hscale = red_r[0] <= (double)kInt16Limit ? 1.0 : 0.0;
     } else if constexpr (std::is_integral_v<Qin>) {
       // integer Q on the float64 walk: exact below kWideSumLimit
       I->big = sa + 1.0;
@@ -521,6 +524,28 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
     for (int u = 0; u < 6; ++u) r->h[u] = (double)H[u];
     r->neo = (int32_t)(-eo);
     r->pad = 0;
+    if constexpr (std::is_same_v<E, int32_t>) {
+      if (v.h16 && I->hscale != 0.0) {
+        // the int16 screen's row: exact Tb / Ta from the linear split of T'
+        auto h16 = [](W x) { return (uint32_t)(uint16_t)(int16_t)x; };
+        HalfRow hr;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          W lo = 0;  // Tb(2k); Tb(2k + 1) adds H_0
+#pragma unroll
+          for (int u = 1; u < 4; ++u) {
+            if (((2 * k) >> u) & 1) lo += H[u];
+          }
+          hr.tb[k] = h16(lo) | (h16(lo + H[0]) << 16);
+        }
+        hr.ta[0] = h16(0) | (h16(H[5]) << 16);
+        hr.ta[1] = h16(H[4]) | (h16(H[4] + H[5]) << 16);
+        hr.neo = (int32_t)(-eo);
+        hr.pad0 = hr.pad1[0] = hr.pad1[1] = 0;
+        hr.tau = 0.0;
+        ((HalfRow*)v.tab)[s] = hr;
+      }
+    }
     if constexpr (std::is_same_v<E, float>) {
       if (v.h16) {
         // the half screen's row: Tb / Ta from the linear split of T'
@@ -540,7 +565,8 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
         const double ta[4] = {0.0, (double)H[4], (double)H[5], (double)H[4] + (double)H[5]};
         hr.ta[0] = h16(ta[0]) | (h16(ta[2]) << 16);
         hr.ta[1] = h16(ta[1]) | (h16(ta[3]) << 16);
-        hr.pad0[0] = hr.pad0[1] = hr.pad1[0] = hr.pad1[1] = 0;
+        hr.neo = 0;
+        hr.pad0 = hr.pad1[0] = hr.pad1[1] = 0;
         hr.tau = (double)eo * hs - I->hmargin;
         ((HalfRow*)v.tab)[s] = hr;
       }
@@ -548,6 +574,9 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
   }
   if constexpr (std::is_same_v<E, float>) {
     if (v.h16) return;  // the half screen reads HalfRow rows only
+  }
+  if constexpr (std::is_same_v<E, int32_t>) {
+    if (v.h16 && I->hscale != 0.0) return;  // the int16 screen reads HalfRow rows only
   }
 #pragma unroll
   for (int u = 0; u < 6; ++u) hs[w][u][lane] = H[u];

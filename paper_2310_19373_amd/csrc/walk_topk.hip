@@ -456,6 +456,174 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
   }
 }
 
+// ---- int32 walk with the int16 screen ---------------------------------------
+//
+// The same split and row layout in exact int16 arithmetic, for instances whose
+// inner bound R_I is at most 32767 (then C', Tb, Ta and every partial sum of
+// them are exact int16 values, and the screen decides exactly as the int32
+// one).  Invalid lanes / inner states carry 32767 and saturating adds, so they
+// can only cause a harmless replay.
+typedef short s2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s2 as_s2(uint32_t x) { return __builtin_bit_cast(s2, x); }
+
+__device__ __forceinline__ int32_t int16_block_min(const HalfRow& r, const s2 (&C)[2][16]) {
+  s2 m[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    s2 s[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const s2 x = as_s2(r.tb[c >> 1]);
+      s[c] = __builtin_elementwise_add_sat(
+          C[a][c], (c & 1) ? __builtin_shufflevector(x, x, 1, 1) : __builtin_shufflevector(x, x, 0, 0));
+    }
+#pragma unroll
+    for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+      for (int c = 0; c < w; ++c) s[c] = __builtin_elementwise_min(s[c], s[c + w]);
+    m[a] = __builtin_elementwise_add_sat(s[0], as_s2(r.ta[a]));
+  }
+  m[0] = __builtin_elementwise_min(m[0], m[1]);
+  const s2 f = __builtin_elementwise_min(m[0], __builtin_shufflevector(m[0], m[0], 1, 0));
+  return (int32_t)f.x;
+}
+
+__device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU& I, uint64_t local, double& lkey,
+                                              uint64_t& lmask, uint64_t& pub, int64_t* myc, int lane) {
+  const bool valid = lane < (1 << I.L);
+  const uint64_t p = (local << I.L) | (uint64_t)lane;
+  int32_t C[64];
+  const int64_t EP = lane_init<int32_t, 64>(v, b, I, local, valid, myc, lane, C);
+  s2 C16[2][16];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int32_t lo = C[c | a << 4], hi = C[c | (a + 2) << 4];  // kIntInvalid -> 32767
+      C16[a][c] = s2{(short)(lo < kInt16Limit ? lo : kInt16Limit), (short)(hi < kInt16Limit ? hi : kInt16Limit)};
+    }
+
+  const double g0 = load_gthr(v, b);
+  if (enc_key(g0) < pub) pub = enc_key(g0);
+  double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
+  int32_t Dp = (int32_t)thr - (int32_t)EP;  // the int32 walk's Dp
+  const uint32_t steps = 1u << I.no;
+  const half_words_t rows = (half_words_t)((const HalfRow*)v.tab + I.tab_off);
+  const int32_t c0 = I.no > 0 ? (int32_t)myc[lane] : 0;
+  const int32_t c1 = I.no > 1 ? (int32_t)myc[kWave + lane] : 0;
+  const int32_t c2 = I.no > 2 ? (int32_t)myc[2 * kWave + lane] : 0;
+
+  auto row = [&](uint32_t t) -> HalfRow {
+    const half_words_t w = rows + (size_t)(t < steps ? t : steps - 1) * (sizeof(HalfRow) / 4);
+    HalfRow r;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r.tb[c] = w[c];
+    r.ta[0] = w[8];
+    r.ta[1] = w[9];
+    r.neo = (int32_t)w[10];
+    return r;
+  };
+  auto retune = [&](double nthr) {
+    Dp += (int32_t)nthr - (int32_t)thr;
+    thr = nthr;
+  };
+  auto body = [&](uint32_t t, const HalfRow& r) {
+    const int32_t m = int16_block_min(r, C16);
+    const bool hit = m <= Dp + r.neo;
+    if (__builtin_expect(ballot(hit) != 0, 0)) {
+      double nthr = thr;
+      const int64_t KE = (int64_t)(int32_t)thr - (int64_t)Dp - (int64_t)r.neo;
+      replay<int32_t>(v, b, I, t, p, valid, KE, nthr, lkey, lmask, pub, myc, lane);
+      retune(nthr);
+    }
+  };
+  auto flip_on = [&](int32_t c) { Dp -= c; };
+  auto flip_off = [&](int32_t c) { Dp += c; };
+  auto flip_sign = [&](bool off, int32_t c) { Dp += off ? c : -c; };
+
+  if (steps < 16) {
+    HalfRow cur = row(0);
+    for (uint32_t t = 0; t < steps; ++t) {
+      if (t) {
+        const int l = __builtin_ctz(t);
+        flip_sign((t >> (l + 1)) & 1, (int32_t)myc[l * kWave + lane]);
+      }
+      wait_rows();
+      const HalfRow nxt = row(t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      body(t, cur);
+      cur = nxt;
+    }
+    return;
+  }
+  // steps >= 16: the float32 walk's unrolled schedule (see walk_unit_h16)
+  HalfRow ev = row(0), od;
+  wait_rows();
+  od = row(1);
+  __builtin_amdgcn_sched_barrier(0);
+  body(0, ev);
+  const uint32_t groups = steps >> 3;
+  for (uint32_t q = 0;; ++q) {
+    const uint32_t t = 8 * q;
+    wait_rows();
+    ev = row(t + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_on(c0);
+    body(t + 1, od);
+    wait_rows();
+    od = row(t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_on(c1);
+    body(t + 2, ev);
+    wait_rows();
+    ev = row(t + 4);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_off(c0);
+    body(t + 3, od);
+    wait_rows();
+    od = row(t + 5);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_sign(q & 1, c2);
+    body(t + 4, ev);
+    wait_rows();
+    ev = row(t + 6);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_on(c0);
+    body(t + 5, od);
+    wait_rows();
+    od = row(t + 7);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_off(c1);
+    body(t + 6, ev);
+    if (q + 1 == groups) {
+      wait_rows();
+      flip_off(c0);
+      body(t + 7, od);
+      break;
+    }
+    wait_rows();
+    const uint32_t t8 = t + 8;
+    const int l8 = __builtin_ctz(t8);
+    const int32_t cl = (int32_t)myc[l8 * kWave + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    ev = row(t8);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_off(c0);
+    body(t + 7, od);
+    wait_rows();
+    od = row(t8 + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    flip_sign((t8 >> (l8 + 1)) & 1, cl);
+    body(t8, ev);
+    if (((q + 1) & 7) == 0) {
+      const double g = load_gthr(v, b);
+      if (enc_key(g) < pub) pub = enc_key(g);
+      if (g < thr) retune(g);
+    }
+  }
+}
+
 template <class E, bool kHalf>
 __device__ __forceinline__ void walk_topk_body(const Views& v) {
   using W = typename Ar<E>::W;
@@ -481,8 +649,17 @@ __device__ __forceinline__ void walk_topk_body(const Views& v) {
     const InstU I = load_inst(v, b);
     if (I.status == 0) {
       const uint64_t local = u - (uint64_t)I.unit_begin + (uint64_t)I.local_off;
-      if constexpr (kHalf) walk_unit_h16(v, b, I, local, lkey, lmask, pub, myc, lane);
-      else walk_unit<E>(v, b, I, local, lkey, lmask, pub, myc, lane);
+      if constexpr (kHalf && std::is_same_v<E, float>) {
+        walk_unit_h16(v, b, I, local, lkey, lmask, pub, myc, lane);
+      } else if constexpr (kHalf) {
+        // int16 screen where the instance's inner bound allows it
+        if (uniform_f64(gp((const Inst*)v.inst)[b].hscale) != 0.0)
+          walk_unit_i16(v, b, I, local, lkey, lmask, pub, myc, lane);
+        else
+          walk_unit<E>(v, b, I, local, lkey, lmask, pub, myc, lane);
+      } else {
+        walk_unit<E>(v, b, I, local, lkey, lmask, pub, myc, lane);
+      }
     }
   }
   if (cur >= 0) flush(v, cur, lkey, lmask, lane);
@@ -500,12 +677,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_h16_kernel(Views v) {
   walk_topk_body<float, true>(v);
 }
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_i16_kernel(Views v) {
+  walk_topk_body<int32_t, true>(v);
+}
 
 }  // namespace
 
 hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s) {
   const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (dt == kDtI32)
+  if (dt == kDtI32 && v.h16)
+    hipLaunchKernelGGL(walk_topk_i16_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
+  else if (dt == kDtI32)
     hipLaunchKernelGGL(walk_topk_kernel<int32_t>, dim3(blocks), dim3(kBlock), 0, s, v);
   else if (dt_wide(dt))
     hipLaunchKernelGGL(walk_topk_f64_kernel, dim3(blocks), dim3(kBlock), 0, s, v);

@@ -91,3 +91,41 @@ def test_batched_and_ranges_same_with_either_screen(gpu_lib):
         _lib.set_tuning(_lib.TUNE_HALF_SCREEN, saved)
     for a, b in zip(*res):
         assert torch.equal(a, b)
+
+
+def _inner_bound(Q):
+    # R_I: sum of |Q| over the walk's six inner rows, both triangles
+    Qs = np.triu(Q).astype(np.int64)
+    Qs = Qs + np.triu(Qs, 1).T
+    return int(np.abs(Qs[:6, :]).sum())
+
+
+@pytest.mark.parametrize("delta", [0, 1])
+def test_int16_screen_at_its_bound(gpu_lib, delta):
+    # int32 Q: the int16 screen runs when R_I <= 32767, the int32 one above;
+    # both must give the oracle's answer, bit for bit
+    n = 20
+    Q = inputs.random_i32(n, 4400, -300, 300)
+    Q[0, 0] = 0
+    Q[0, 0] = 32767 + delta - _inner_bound(Q)
+    assert _inner_bound(Q) == 32767 + delta and abs(int(Q[0, 0])) < 2**15
+    print(f"int16 screen bound R_I={_inner_bound(Q)}", flush=True)
+    _check(Q, 10)
+
+
+def test_int_large_inner_rows_fall_back(gpu_lib):
+    Q = inputs.random_i32(21, 4500, -5000, 5000)
+    assert _inner_bound(Q) > 32767
+    _check(Q, 7)
+
+
+def test_int_extreme_int16_values(gpu_lib):
+    # inner states whose screened values reach about +-32767
+    n = 18
+    Q = np.zeros((n, n), np.int32)
+    Q[0, 0] = -16000
+    Q[1, 1] = -16000
+    Q[0, 1] = -383  # C'(0b11) = -32383; R_I counts Q01 twice: 32766
+    Q[6:, 6:] = np.triu(inputs.random_i32(n - 6, 4600, -40, 40))
+    assert _inner_bound(Q) <= 32767
+    _check(Q, 12)
