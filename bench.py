@@ -127,7 +127,8 @@ def _time(fn, reps):
 
 
 def float_ops_per_state():
-    """Lane-ops per state of the float32 walk as the library is tuned now."""
+    """Lane-ops per state of the float32 walk (and of a single int32 solve
+    whose inner rows fit the int16 screen) as the library is tuned now."""
     from paper_2310_19373_amd import _lib
 
     return HALF_OPS_PER_STATE if _lib.get_tuning(_lib.TUNE_HALF_SCREEN) > 0 else ALG_OPS_PER_STATE
@@ -485,7 +486,8 @@ def main():
             "single_n20_f32": extra_single(dev, "n=20 float32 N(0,1) (seed 0), k=8", inputs.single_n20_f32(), 8,
                                            _lib.QUBO_F32, 50, ops_per_state=float_ops_per_state()),
             "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
-                                           inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10),
+                                           inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10,
+                                           ops_per_state=float_ops_per_state()),
             "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64, k=16, float64 walk",
                                            inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64,
                                            3, ops_per_state=3.0),
