@@ -343,7 +343,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true",
                     help="also time the batched and log-partition workloads against one call per instance")
-    ap.add_argument("--only", choices=("batched", "logz", "n40_f64"),
+    ap.add_argument("--only", choices=("batched", "logz", "n40_f64", "n32_i32"),
                     help="run only that secondary workload, without the one-call-per-instance loop")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched workload: keep the current launch shape (knobs or QUBO_BF_* variables) untuned")
@@ -377,6 +377,9 @@ def main():
     if args.only:
         if args.only == "batched":
             res = extra_batched(dev, plain_loop=False, tune=not args.no_tune)
+        elif args.only == "n32_i32":
+            res = extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16", inputs.single_n32_i32(), 16,
+                               _lib.QUBO_I32, 10, ops_per_state=float_ops_per_state())
         elif args.only == "n40_f64":
             res = extra_single(dev, "n=40 planted (seed 2) as float64, k=16, float64 walk",
                                inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64, 3,
