@@ -244,9 +244,9 @@ const char* qubo_version(void);
  *   QUBO_TUNE_HALF_SCREEN         float32 top-k walks: 1 screens each block of
  *                                 64 states in packed float16 (with a margin
  *                                 that keeps every block the float32 screen
- *                                 passes); single int32 solves whose inner
- *                                 rows sum to at most 32767 in |Q| screen in
- *                                 exact int16; -1: float32 / int32 screens
+ *                                 passes); int32 instances whose inner rows
+ *                                 sum to at most 32767 in |Q| screen in exact
+ *                                 int16; -1: float32 / int32 screens
  *                                 (results are identical: passing blocks are
  *                                 replayed exactly)
  * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)

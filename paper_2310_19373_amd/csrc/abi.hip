@@ -333,12 +333,11 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
              uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
   Views v = v0;
   // float32 walks screen blocks in packed float16 (the step tables then hold
-  // HalfRow rows, 64 of the 256 bytes a float32 row takes); a single int32
-  // instance screens in exact int16 when its inner bound allows (in a batch
-  // the two row layouts would overlap between instances, so batches keep
-  // the int32 screen)
+  // HalfRow rows, 64 of the 256 bytes a float32 row takes); int32 instances
+  // screen in exact int16 where their inner bound allows (HalfRow rows in the
+  // int32 rows' 256-byte slots, so both kinds share one layout in a batch)
   const bool half = tuning().half_screen > 0 && pp.inner == kInner;
-  v.h16 = (half && (dt == kDtF32 || (dt == kDtI32 && v.batch == 1))) ? 1 : 0;
+  v.h16 = (half && (dt == kDtF32 || dt == kDtI32)) ? 1 : 0;
   int waves = grid_waves();
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;

@@ -131,6 +131,10 @@ struct HalfRow {
   uint32_t pad1[2];
 };
 static_assert(sizeof(HalfRow) == 64, "HalfRow is one 64-byte scalar load");
+// The int16 rows sit in the int32 rows' 256-byte step slots (only their first
+// 64 bytes used), so that in a batch instances with either screen share one
+// table layout; the float32 walk's float16 rows are packed at 64 bytes.
+constexpr int kInt16RowStride = 4;  // in HalfRow units
 
 struct StepRec {
   double eo;      // E_O(g(t))

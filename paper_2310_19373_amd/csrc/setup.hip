@@ -543,7 +543,7 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
         hr.neo = (int32_t)(-eo);
         hr.pad0 = hr.pad1[0] = hr.pad1[1] = 0;
         hr.tau = 0.0;
-        ((HalfRow*)v.tab)[s] = hr;
+        ((HalfRow*)v.tab)[s * kInt16RowStride] = hr;
       }
     }
     if constexpr (std::is_same_v<E, float>) {

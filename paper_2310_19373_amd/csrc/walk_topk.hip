@@ -458,7 +458,8 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
 
 // ---- int32 walk with the int16 screen ---------------------------------------
 //
-// The same split and row layout in exact int16 arithmetic, for instances whose
+// The same split and row layout (rows in 256-byte step slots) in exact int16
+// arithmetic, for instances whose
 // inner bound R_I is at most 32767 (then C', Tb, Ta and every partial sum of
 // them are exact int16 values, and the screen decides exactly as the int32
 // one).  Invalid lanes / inner states carry 32767 and saturating adds, so they
@@ -509,13 +510,13 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
   double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
   int32_t Dp = (int32_t)thr - (int32_t)EP;  // the int32 walk's Dp
   const uint32_t steps = 1u << I.no;
-  const half_words_t rows = (half_words_t)((const HalfRow*)v.tab + I.tab_off);
+  const half_words_t rows = (half_words_t)((const HalfRow*)v.tab + I.tab_off * kInt16RowStride);
   const int32_t c0 = I.no > 0 ? (int32_t)myc[lane] : 0;
   const int32_t c1 = I.no > 1 ? (int32_t)myc[kWave + lane] : 0;
   const int32_t c2 = I.no > 2 ? (int32_t)myc[2 * kWave + lane] : 0;
 
   auto row = [&](uint32_t t) -> HalfRow {
-    const half_words_t w = rows + (size_t)(t < steps ? t : steps - 1) * (sizeof(HalfRow) / 4);
+    const half_words_t w = rows + (size_t)(t < steps ? t : steps - 1) * (kInt16RowStride * sizeof(HalfRow) / 4);
     HalfRow r;
 #pragma unroll
     for (int c = 0; c < 8; ++c) r.tb[c] = w[c];

@@ -129,3 +129,27 @@ def test_int_extreme_int16_values(gpu_lib):
     Q[6:, 6:] = np.triu(inputs.random_i32(n - 6, 4600, -40, 40))
     assert _inner_bound(Q) <= 32767
     _check(Q, 12)
+
+
+def test_int_batch_mixes_both_screens(gpu_lib):
+    # a batch whose instances fall on either side of the int16 bound: the two
+    # kinds of rows share the table layout
+    rng = np.random.default_rng(4700)
+    ns = rng.integers(8, 21, 40).astype(np.int32)
+    Q = np.zeros((40, 20, 20), np.int32)
+    for b, n in enumerate(ns):
+        hi = 30 if b % 2 == 0 else 4000
+        Q[b, :n, :n] = np.triu(rng.integers(-hi, hi + 1, (n, n)))
+    saved = _lib.get_tuning(_lib.TUNE_HALF_SCREEN)
+    try:
+        res = []
+        for h in (1, -1):
+            _lib.set_tuning(_lib.TUNE_HALF_SCREEN, h)
+            e, m = api.solve_batched(Q, ns, 5)
+            res.append((e.cpu().numpy(), m.cpu().numpy()))
+    finally:
+        _lib.set_tuning(_lib.TUNE_HALF_SCREEN, saved)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    for b, n in enumerate(ns):
+        E, M = oracle.topk(Q[b, :n, :n], 5)
+        assert _u64(res[0][1][b]) == _u64(M) and np.array_equal(res[0][0][b], E), b
