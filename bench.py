@@ -126,20 +126,24 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def float_ops_per_state():
-    """Lane-ops per state of the float32 walk (and of a single int32 solve
-    whose inner rows fit the int16 screen) as the library is tuned now."""
+def float_ops_per_state(wide: bool = False):
+    """Lane-ops per state of the walk as the library is tuned now: the half
+    screen's (float32, float64 and int64 Q, and int32 Q whose inner rows fit
+    int16), else the float32 / int32 screen's, or the float64 walk's 3 (a
+    64-bit DPP move, v_add_f64, v_min_f64) for wide Q."""
     from paper_2310_19373_amd import _lib
 
-    return HALF_OPS_PER_STATE if _lib.get_tuning(_lib.TUNE_HALF_SCREEN) > 0 else ALG_OPS_PER_STATE
+    if _lib.get_tuning(_lib.TUNE_HALF_SCREEN) > 0:
+        return HALF_OPS_PER_STATE
+    return 3.0 if wide else ALG_OPS_PER_STATE
 
 
 def extra_single(dev, name, Q, k, dt, reps, ops_per_state=ALG_OPS_PER_STATE):
     """One full qubo_bf_solve per call on another configuration; states/s of
     the call and the walk kernel's VALU roofline fraction (ops_per_state
-    lane-ops per state: 68/64 for the float32 walk's half screen, 1.5 for its
-    float32 screen and the int32 walk, 3 for the float64 walk; HIP events
-    around the walk launch)."""
+    lane-ops per state: 66/64 for the half screen, 1.5 for the float32 and
+    int32 screens, 3 for the float64 walk's; HIP events around the walk
+    launch)."""
     import torch
 
     from paper_2310_19373_amd import _lib
@@ -381,9 +385,9 @@ def main():
             res = extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16", inputs.single_n32_i32(), 16,
                                _lib.QUBO_I32, 10, ops_per_state=float_ops_per_state())
         elif args.only == "n40_f64":
-            res = extra_single(dev, "n=40 planted (seed 2) as float64, k=16, float64 walk",
+            res = extra_single(dev, "n=40 planted (seed 2) as float64 Q, k=16",
                                inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64, 3,
-                               ops_per_state=3.0)
+                               ops_per_state=float_ops_per_state(wide=True))
         else:
             res = extra_logz(dev, plain_loop=False)
         print(json.dumps({args.only: res}), flush=True)
@@ -491,9 +495,9 @@ def main():
             "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
                                            inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10,
                                            ops_per_state=float_ops_per_state()),
-            "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64, k=16, float64 walk",
+            "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64 Q, k=16",
                                            inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64,
-                                           3, ops_per_state=3.0),
+                                           3, ops_per_state=float_ops_per_state(wide=True)),
             "batched": extra_batched(dev), "logz": extra_logz(dev), "ranges": extra_ranges(dev),
             "moments": extra_moments(dev), "sample": extra_sample(dev)}
     print(json.dumps(out), flush=True)

@@ -241,12 +241,13 @@ const char* qubo_version(void);
  *   QUBO_TUNE_SEED_SWEEPS         descent passes of the per-instance threshold
  *                                 seed before a top-k walk; -1: no seeding
  *                                 (speed only: results are identical)
- *   QUBO_TUNE_HALF_SCREEN         float32 top-k walks: 1 screens each block of
- *                                 64 states in packed float16 (with a margin
- *                                 that keeps every block the float32 screen
+ *   QUBO_TUNE_HALF_SCREEN         top-k walks: 1 screens each block of 64
+ *                                 states of float32, float64 and int64 Q in
+ *                                 packed float16 (with a margin that keeps
+ *                                 every block a float32 / float64 screen
  *                                 passes); int32 instances whose inner rows
  *                                 sum to at most 32767 in |Q| screen in exact
- *                                 int16; -1: float32 / int32 screens
+ *                                 int16; -1: float32 / int32 / float64 screens
  *                                 (results are identical: passing blocks are
  *                                 replayed exactly)
  * Environment variables of the same names (QUBO_BF_SINGLE_OUTER_BITS, ...)

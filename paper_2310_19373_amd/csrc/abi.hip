@@ -255,9 +255,9 @@ PlanParams single_params(int kp, int n, int dt) {
   // from n = 33 so that a grid of ~3000 waves gets several units each.
   // Measured with the float32 walk's half screen: n=24 -> 8, n=28 -> 10,
   // n=30..32 -> 11, n=33..36 -> 14 (n=38 is flat; n=40 reaches 16 unit bits
-  // either way).  The walks with a costlier step (int32, float32 screen,
-  // float64) do best with one bit fewer: n=32 -> 12, n=34 -> 13.
-  const bool half = (dt == kDtF32 || dt == kDtI32) && t.half_screen > 0;
+  // either way).  The walks with a costlier step (the float32 and int32
+  // screens) do best with one bit fewer: n=32 -> 12, n=34 -> 13.
+  const bool half = t.half_screen > 0;
   const int mid_cap = half ? 11 : 12, big = half ? 14 : 13;
   const int want = n >= 33 ? big : (n - 18 > mid_cap ? mid_cap : (n - 18 > 8 ? n - 18 : 8));
   pp.ub_min = clampi(t.single_unit < want ? t.single_unit : want, 0, 62);
@@ -318,11 +318,11 @@ int check_k(int k, bool exact) {
 // The float64 walk (float64 and int64 Q) takes five inner bits and 8-byte
 // table entries.
 PlanParams with_dt(PlanParams pp, qubo_dtype dt) {
-  if (dt_wide(dt)) {
+  if (dt_wide(dt) && tuning().half_screen <= 0) {
     pp.inner = kInnerWide;
     pp.tab_elem = 8;
   } else {
-    pp.tab_elem = 4;
+    pp.tab_elem = 4;  // float32 / int32 rows, or the half screen's (float64 and int64 Q too)
   }
   return pp;
 }
@@ -332,12 +332,13 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
              int dt, int k, PlanParams pp, int64_t units_hint, int64_t steps_hint, void* energies,
              uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
   Views v = v0;
-  // float32 walks screen blocks in packed float16 (the step tables then hold
-  // HalfRow rows, 64 of the 256 bytes a float32 row takes); int32 instances
-  // screen in exact int16 where their inner bound allows (HalfRow rows in the
-  // int32 rows' 256-byte slots, so both kinds share one layout in a batch)
+  // float32, float64 and int64 Q screen blocks in packed float16 (the step
+  // tables then hold HalfRow rows, 64 of the 256 bytes a float32 row takes);
+  // int32 instances screen in exact int16 where their inner bound allows
+  // (HalfRow rows in the int32 rows' 256-byte slots, so both kinds share one
+  // layout in a batch)
   const bool half = tuning().half_screen > 0 && pp.inner == kInner;
-  v.h16 = (half && (dt == kDtF32 || dt == kDtI32)) ? 1 : 0;
+  v.h16 = half ? 1 : 0;
   int waves = grid_waves();
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;

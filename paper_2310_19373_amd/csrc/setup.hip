@@ -234,6 +234,8 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
       // so the walk is exact (eps = 0) and ties are resolved like the int path.
       if (!red_frac[0] && sa <= 16777216.0) I->eps = 0.0;
       if (red_bad[0]) I->status = kErrNonfinite;
+    }
+    if constexpr (!std::is_same_v<E, int32_t>) {
       // Half-precision screen.  Every screened value and partial sum (C',
       // Tb, Ta, C' + Tb, C' + Tb + Ta) is a partial sum of the inner rows, so
       // at most R_I in magnitude; scaled by hs = 2^s with R_I hs in
@@ -251,6 +253,8 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
         I->hscale = ldexp(1.0, 13 - e);
       }
       I->hmargin = I->hscale * (0x1p-8 * red_r[0] + 0x1p-50 * sa) + 0x1p-10;
+      // (For the float64 walk the same bound holds against its float64 screen,
+      // so its eps and certificate are unchanged as well.)
     }
   }
 }
@@ -546,7 +550,7 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
         ((HalfRow*)v.tab)[s * kInt16RowStride] = hr;
       }
     }
-    if constexpr (std::is_same_v<E, float>) {
+    if constexpr (!std::is_same_v<E, int32_t>) {
       if (v.h16) {
         // the half screen's row: Tb / Ta from the linear split of T'
         const double hs = I->hscale;
@@ -572,7 +576,7 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
       }
     }
   }
-  if constexpr (std::is_same_v<E, float>) {
+  if constexpr (!std::is_same_v<E, int32_t>) {
     if (v.h16) return;  // the half screen reads HalfRow rows only
   }
   if constexpr (std::is_same_v<E, int32_t>) {

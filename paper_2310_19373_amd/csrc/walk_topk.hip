@@ -690,10 +690,10 @@ hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s) {
     hipLaunchKernelGGL(walk_topk_i16_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
   else if (dt == kDtI32)
     hipLaunchKernelGGL(walk_topk_kernel<int32_t>, dim3(blocks), dim3(kBlock), 0, s, v);
+  else if (v.h16)  // float32, float64 and int64 Q
+    hipLaunchKernelGGL(walk_topk_h16_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
   else if (dt_wide(dt))
     hipLaunchKernelGGL(walk_topk_f64_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
-  else if (v.h16)
-    hipLaunchKernelGGL(walk_topk_h16_kernel, dim3(blocks), dim3(kBlock), 0, s, v);
   else
     hipLaunchKernelGGL(walk_topk_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, v);
   return hipGetLastError();

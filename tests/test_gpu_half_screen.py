@@ -153,3 +153,16 @@ def test_int_batch_mixes_both_screens(gpu_lib):
     for b, n in enumerate(ns):
         E, M = oracle.topk(Q[b, :n, :n], 5)
         assert _u64(res[0][1][b]) == _u64(M) and np.array_equal(res[0][0][b], E), b
+
+
+@pytest.mark.parametrize("kind", ["f64", "i64"])
+def test_wide_inputs_same_with_either_screen(gpu_lib, kind):
+    # float64 / int64 Q: the half screen against the float64 walk's own
+    # screen, both against the oracle
+    rng = np.random.default_rng(4800)
+    n = 23
+    if kind == "f64":
+        Q = np.triu(rng.standard_normal((n, n)) / np.sqrt(n) + 1e-9 * rng.standard_normal((n, n)))
+    else:
+        Q = np.triu(rng.integers(-2**36, 2**36, (n, n), dtype=np.int64))
+    _check(Q, 11)
