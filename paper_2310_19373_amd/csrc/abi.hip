@@ -49,7 +49,7 @@ struct Tuning {
   int chunk_batched = 8;
   int dyn = 1;
   int logz_factored = 1;
-  int seed_sweeps = 2;
+  int seed_sweeps = 1;
   int half_screen = 1;
 };
 
