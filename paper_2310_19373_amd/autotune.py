@@ -10,7 +10,7 @@ The best choice depends on the mix of instance sizes, so it is measured on the
 caller's own batch:
 
     res = autotune.tune_batched(Qpad, ns, k=1)     # applies the best setting
-    res.best  -> {"batched_outer": 8, "waves_per_cu": 12, "chunk_batched": 8}
+    res.best  -> {"batched_outer": 9, "waves_per_cu": 16, "chunk_batched": 2}
 
 The search is a coordinate descent from the current setting over a small grid
 per knob.  Every candidate's outputs (energies, masks, status) must equal those
@@ -40,13 +40,13 @@ KNOBS = {
 
 BATCHED_SPACE = {
     "batched_outer": (6, 7, 8, 9, 10),
-    "waves_per_cu": (4, 8, 12),
+    "waves_per_cu": (8, 12, 16),
     "chunk_batched": (2, 4, 8, 16),
 }
 
 SINGLE_SPACE = {
-    "single_outer": (10, 11, 12, 13, 14),
-    "waves_per_cu": (8, 12),
+    "single_outer": (9, 10, 11, 12),
+    "waves_per_cu": (12, 16),
     "chunk_single": (1, 2, 4, 8),
 }
 

@@ -43,7 +43,7 @@ struct Tuning {
   int single_outer = 12;
   int single_unit = 14;
   int batched_outer = 8;
-  int waves_per_cu = 12;
+  int waves_per_cu = 0;  // 0: 16 for the half-screen walk, 12 for the others
   int kprime = 0;
   int chunk_single = 2;
   int chunk_batched = 8;
@@ -102,8 +102,11 @@ int device_cus() {
   return cache[dev];
 }
 
-int grid_waves() {
-  long w = (long)device_cus() * clampi(tuning().waves_per_cu, 1, 32);
+// Waves of a persistent grid: the knob, else `auto_per_cu` per CU (the
+// resident count of the kernel launched).
+int grid_waves(int auto_per_cu = 12) {
+  const int per_cu = tuning().waves_per_cu > 0 ? tuning().waves_per_cu : auto_per_cu;
+  long w = (long)device_cus() * clampi(per_cu, 1, 32);
   if (w > kMaxGridWaves) w = kMaxGridWaves;
   return (int)(w - w % kWavesPerBlock);
 }
@@ -339,7 +342,8 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
   // layout in a batch)
   const bool half = tuning().half_screen > 0 && pp.inner == kInner;
   v.h16 = half ? 1 : 0;
-  int waves = grid_waves();
+  // the half-screen walk (float32, float64 and int64 Q) runs 4 waves per SIMD
+  int waves = grid_waves(v.h16 && dt != kDtI32 ? 16 : 12);
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;
     waves += (kWavesPerBlock - waves % kWavesPerBlock) % kWavesPerBlock;

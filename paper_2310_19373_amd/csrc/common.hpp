@@ -29,7 +29,9 @@ namespace qbf {
 constexpr int kWave = 64;
 constexpr int kInner = 6;                 // inner bits of the top-k / logZ-forward walks
 constexpr int kInnerStates = 1 << kInner;  // 64 table entries per lane
-constexpr int kMaxOuter = 14;              // outer bits per work unit (upper bound)
+constexpr int kMaxOuter = 12;              // outer bits per work unit (upper bound); keeps
+                                           // the per-wave LDS rows below at 20, so that
+                                           // four 4-wave blocks (40 KB each) fit per CU
 // Per-wave LDS table of the walks, rows of 64 lane entries: rows [0, no) hold
 // the outer cross fields c_l, rows kCIRow.. the six inner cross fields, row
 // kTileRow the per-unit tile sums exchanged between lanes.

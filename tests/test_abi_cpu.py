@@ -88,9 +88,11 @@ def test_tuning_knobs_roundtrip():
     L = _lib.lib()
     old = L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS)
     before = L.qubo_bf_workspace_size(40, 16, 0)
+    assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 9) == 0
+    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == 9
+    assert L.qubo_bf_workspace_size(40, 16, 0) != before   # 2^9-step tables, 8x the units
     assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 14) == 0
-    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == 14
-    assert L.qubo_bf_workspace_size(40, 16, 0) > before
+    assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == 12  # clamped to the maximum
     assert L.qubo_bf_set_tuning(_lib.TUNE_SINGLE_OUTER_BITS, 0) == 0
     assert L.qubo_bf_get_tuning(_lib.TUNE_SINGLE_OUTER_BITS) == old
     assert L.qubo_bf_set_tuning(99, 1) == -1
