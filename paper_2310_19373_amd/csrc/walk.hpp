@@ -209,9 +209,14 @@ __device__ __forceinline__ double load_gthr(const Views& v, int b) {
 // and returns E_P(p).  The lane-bit parts come from the instance's lane table;
 // the tile-bit parts are summed lane-parallel (lane t takes row t, lane t also
 // tile row t for E_tile) with independent loads, and exchanged through LDS.
-template <class E, int NB>
-__device__ __forceinline__ typename Ar<E>::W lane_init(const Views& v, int b, const InstU& I, uint64_t local,
-                                                       bool valid, typename Ar<E>::W* myc, int lane, E (&C)[NB]) {
+//
+// lane_init_with hands each inner entry to sink(j, ok, C'(j)) (ok: a valid
+// lane and inner state) instead of storing a table, so a caller can keep the
+// entries in another form without the 64-entry table ever being live.
+template <class E, int NB, bool kLaneEI = false, class Sink>
+__device__ __forceinline__ typename Ar<E>::W lane_init_with(const Views& v, int b, const InstU& I, uint64_t local,
+                                                            bool valid, typename Ar<E>::W* myc, int lane,
+                                                            Sink&& sink) {
   using W = typename Ar<E>::W;
   const int pos0 = I.B + I.no;
   const int tp0 = pos0 + I.L;  // first tile bit
@@ -259,15 +264,30 @@ __device__ __forceinline__ typename Ar<E>::W lane_init(const Views& v, int b, co
     myc[(kCIRow + u) * kWave + lane] = cI[u];
   }
   for (int l = 0; l < I.no; ++l) myc[l * kWave + lane] = lt[8 + l] + myc[kTileRow * kWave + I.B + l];
+  // kLaneEI: lane j loads E_I(j) (one coalesced load) and the loop reads it
+  // back by lane, for kernels at 128 VGPRs where 64 entries loaded per lane
+  // (128 VGPRs in flight) would spill
+  const W eil = (kLaneEI && lane < NB) ? ei[lane] : (W)0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    W cj = ei[j];
+    W cj;
+    if constexpr (!kLaneEI) cj = ei[j];
+    else if constexpr (std::is_same_v<W, double>) cj = readlane_f64(eil, j);
+    else cj = readlane_i64(eil, j);
 #pragma unroll
     for (int u = 0; u < 6; ++u)
       if ((j >> u) & 1) cj += cI[u];
-    C[j] = (valid && j < (1 << I.B)) ? (E)cj : Ar<E>::inv();
+    sink(j, valid && j < (1 << I.B), cj);
   }
   return EP;
+}
+
+template <class E, int NB>
+__device__ __forceinline__ typename Ar<E>::W lane_init(const Views& v, int b, const InstU& I, uint64_t local,
+                                                       bool valid, typename Ar<E>::W* myc, int lane, E (&C)[NB]) {
+  using W = typename Ar<E>::W;
+  return lane_init_with<E, NB>(v, b, I, local, valid, myc, lane,
+                               [&](int j, bool ok, W cj) { C[j] = ok ? (E)cj : Ar<E>::inv(); });
 }
 
 }  // namespace qbf

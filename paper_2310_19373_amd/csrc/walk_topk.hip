@@ -316,19 +316,16 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
   const double hs = uniform_f64(gp((const Inst*)v.inst)[b].hscale);
   const double his = 1.0 / hs;  // exact: hs is a power of two
 
-  float C[64];
-  const double EP = lane_init<float, 64>(v, b, I, local, valid, myc, lane, C);
-  // C' * hs: an exact float32 scaling (|C' hs| < 2^13), then one rounding
+  // C'(j), j = c | a << 4, as float16 pairs (a, a + 2) of C' * hs: float32
+  // rounding, an exact float32 scaling (|C' hs| < 2^13), one float16 rounding
   int hexp;
   frexp(hs, &hexp);
   hexp -= 1;  // hs = 2^hexp
   h2 C16[2][16];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      C16[a][c] = h2{(_Float16)__builtin_ldexpf(C[c | a << 4], hexp),
-                     (_Float16)__builtin_ldexpf(C[c | (a + 2) << 4], hexp)};
+  const double EP = lane_init_with<float, 64, true>(v, b, I, local, valid, myc, lane, [&](int j, bool ok, double cj) {
+    const float f = ok ? (float)cj : __builtin_inff();
+    C16[(j >> 4) & 1][j & 15][j >> 5] = (_Float16)__builtin_ldexpf(f, hexp);
+  });
 
   const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
@@ -494,16 +491,11 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
                                               uint64_t& lmask, uint64_t& pub, int64_t* myc, int lane) {
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
-  int32_t C[64];
-  const int64_t EP = lane_init<int32_t, 64>(v, b, I, local, valid, myc, lane, C);
+  // C'(j), j = c | a << 4, as int16 pairs (a, a + 2); invalid entries 32767
   s2 C16[2][16];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int32_t lo = C[c | a << 4], hi = C[c | (a + 2) << 4];  // kIntInvalid -> 32767
-      C16[a][c] = s2{(short)(lo < kInt16Limit ? lo : kInt16Limit), (short)(hi < kInt16Limit ? hi : kInt16Limit)};
-    }
+  const int64_t EP = lane_init_with<int32_t, 64>(v, b, I, local, valid, myc, lane, [&](int j, bool ok, int64_t cj) {
+    C16[(j >> 4) & 1][j & 15][j >> 5] = (short)(ok ? cj : kInt16Limit);
+  });
 
   const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
