@@ -46,7 +46,7 @@ struct Tuning {
   int waves_per_cu = 0;  // 0: 16 for the half-screen walk, 12 for the others
   int kprime = 0;
   int chunk_single = 2;
-  int chunk_batched = 8;
+  int chunk_batched = 2;
   int dyn = 1;
   int logz_factored = 1;
   int seed_sweeps = 1;
