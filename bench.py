@@ -366,8 +366,8 @@ def main():
         print(walk_sources_sha256())
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the enumeration shards by prefix "
-              "bits across GPUs, which this build does not run", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one device; "
+              "across GPUs the enumeration would shard its work units by their top prefix bits", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,0 +1,45 @@
+"""bench.py's host-side contract, on the CPU: it refuses more than one GPU
+with a message, prints the walk sources' hash, and the committed counter
+summary that its traffic figure comes from was taken on the current walk
+sources (else the figure would be reported as null)."""
+import os
+import re
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=300, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_sources_sha_matches_the_module():
+    r = _run("--sources-sha")
+    assert r.returncode == 0
+    sha = r.stdout.strip()
+    assert re.fullmatch(r"[0-9a-f]{64}", sha)
+    assert sha == bench.walk_sources_sha256()
+
+
+def test_committed_counters_match_the_walk_sources():
+    # the n=40 counter summary names the sources it was measured on; a change
+    # to the walk without a new profile would make bench report traffic null
+    traffic = bench.committed_traffic()
+    assert traffic is not None and traffic > 0
+
+
+def test_algorithmic_work_per_state():
+    # 66 packed instructions per 64 states for the half screen; 1.5 per state
+    # (one DPP add, half a three-input minimum) for the float32 screen
+    assert bench.HALF_OPS_PER_STATE == 66 / 64
+    assert bench.ALG_OPS_PER_STATE == 1.5
