@@ -85,9 +85,9 @@ struct Inst {
   double big;               // threshold that no state exceeds
   double eps;               // bound on |f32 walk value - exact value| (float path)
   double sign;              // +1, or -1 when the walk runs on -Q
-  // half-width screen.  float32 walk: table values are scaled by hscale (a
-  // power of two putting the inner bound R_I in [2^12, 2^13)) and the
-  // screen's threshold is raised by hmargin (scaled units).  int32 walk:
+  // half-width screen.  float32 / float64 / int64 Q: table values are scaled
+  // by hscale (a power of two putting the inner bound R_I in [2^12, 2^13))
+  // and the screen's threshold is raised by hmargin (scaled units).  int32 Q:
   // hscale = 1 when R_I <= 32767 (every screened value is an exact int16),
   // else 0 (the instance keeps the int32 screen).
   double hscale;
@@ -121,9 +121,9 @@ struct Header {
 // One outer step of a half-width screen (64 bytes, read with scalar loads):
 // the inner 6 bits j = b | a << 4 split into 4 + 2, and T'(j) = Tb(b) + Ta(a)
 // (T' is linear in the inner bits).  tb[k] holds (Tb(2k), Tb(2k + 1)), ta[a]
-// holds (Ta(a), Ta(a + 2)).  float32 walk: float16 of the scaled values, and
-// tau = hscale * E_O(g(t)) - hmargin; int32 walk: exact int16 values, and
-// neo = -E_O(g(t)).
+// holds (Ta(a), Ta(a + 2)).  float32 / float64 / int64 Q: float16 of the
+// scaled values, and tau = hscale * E_O(g(t)) - hmargin; int32 Q: exact int16
+// values, and neo = -E_O(g(t)).
 struct HalfRow {
   uint32_t tb[8];
   uint32_t ta[2];

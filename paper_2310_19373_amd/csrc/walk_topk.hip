@@ -12,11 +12,14 @@
 //     bit l = CTZ(t) (Sec. 2.2), turning it on iff bit l+1 of t is 0; the
 //     per-lane scalar KE = E_P + X_PO + E_O moves by +-c_l plus the uniform
 //     E_O(g(t)) (the single-flip update of Eq. 2, Sec. 2.1, restricted to the prefix/outer cross terms);
-//   * 64 inner states per step: e_j = C'(j) + T'(g(t); j), with T' broadcast
-//     across each 16-lane row by DPP (one v_add_*_dpp per state) and folded by
-//     v_min3 (half an instruction per state); the float64 walk takes 32 inner
-//     states per step at three instructions per state (v_mov_b64_dpp,
-//     v_add_f64, v_min_f64);
+//   * 64 inner states per step: e_j = C'(j) + T'(g(t); j).  The default
+//     screens them in packed float16 (int16 for int32 Q) with T' split into
+//     two scalar-register tables (walk_unit_h16 / walk_unit_i16 below, about
+//     one packed instruction per state); the float32 / int32 screen
+//     broadcasts T' across each 16-lane row by DPP (one v_add_*_dpp per state)
+//     and folds by v_min3 (half an instruction per state); the float64 walk
+//     takes 32 inner states per step at three instructions per state
+//     (v_mov_b64_dpp, v_add_f64, v_min_f64);
 //   * if the block minimum can beat the wave's threshold (rare after warm-up),
 //     the block is replayed with exact float64 / int64 keys and the candidates
 //     are inserted into the wave's sorted top-K' list (lexicographic (energy,
@@ -259,7 +262,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   }
 }
 
-// ---- float32 walk with the half-precision screen ----------------------------
+// ---- the walk with the half-precision screen (float32, float64, int64 Q) ---
 //
 // Same walk, same replay, same thresholds; only the per-step block screen
 // changes.  The inner index j = b | a << 4 splits 4 + 2 and T'(g(t); j) =
@@ -272,8 +275,9 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
 // 30 v_pk_min_f16, 2 v_pk_add_f16 for + Ta and 2 minimums: 66 instructions
 // for 64 states.  The float64 offset Dp is kept scaled by hscale (exact: a
 // power of two), and the block passes when m <= Dp - tau, tau = hscale E_O -
-// hmargin.  hmargin makes the half screen pass every block the float32 screen
-// passes; the replay recomputes passing blocks with exact keys.
+// hmargin.  hmargin makes the half screen pass every block the float32 (or
+// float64) screen passes; the replay recomputes passing blocks with exact
+// keys.
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(4))) uint32_t* half_words_t;
 
