@@ -230,8 +230,9 @@ const char* qubo_version(void);
  *                                 the float32 half screen)
  *   QUBO_TUNE_BATCHED_OUTER_BITS  max outer bits per work unit, batched / logZ
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
- *                                 (default: 16 for the half-screen walk of
- *                                 float32, float64 and int64 Q, 12 otherwise)
+ *                                 (0, the default, reads back as 0 and means
+ *                                 16 for the half-screen walk of float32,
+ *                                 float64 and int64 Q, 12 otherwise)
  *   QUBO_TUNE_KPRIME              candidate list length override (float path;
  *                                 values below k make the certificate fail)
  *   QUBO_TUNE_CHUNK_SINGLE        work units per queue pull, single solve
