@@ -397,7 +397,8 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
   __builtin_amdgcn_sched_barrier(0);
   body(0, ev);
   const uint32_t groups = steps >> 3;
-  for (uint32_t q = 0;; ++q) {
+  // steps 8q+1 .. 8q+6 of group q
+  auto six = [&](uint32_t q) {
     const uint32_t t = 8 * q;
     wait_rows();
     ev = row(t + 2);
@@ -429,12 +430,12 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
     __builtin_amdgcn_sched_barrier(0);
     flip_off(c1);
     body(t + 6, ev);
-    if (q + 1 == groups) {
-      wait_rows();
-      flip_off(c0);
-      body(t + 7, od);
-      break;
-    }
+  };
+  // every group but the last ends with steps 8q+7 and 8q+8 (the flip of bit
+  // 3 + CTZ(q+1)); the last group, peeled, ends with step 8q+7
+  for (uint32_t q = 0; q + 1 < groups; ++q) {
+    six(q);
+    const uint32_t t = 8 * q;
     wait_rows();
     const uint32_t t8 = t + 8;
     const int l8 = __builtin_ctz(t8);
@@ -455,6 +456,10 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
       if (g < thr) retune(g);
     }
   }
+  six(groups - 1);
+  wait_rows();
+  flip_off(c0);
+  body(8 * (groups - 1) + 7, od);
 }
 
 // ---- int32 walk with the int16 screen ---------------------------------------
@@ -561,7 +566,7 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
   __builtin_amdgcn_sched_barrier(0);
   body(0, ev);
   const uint32_t groups = steps >> 3;
-  for (uint32_t q = 0;; ++q) {
+  auto six = [&](uint32_t q) {  // steps 8q+1 .. 8q+6
     const uint32_t t = 8 * q;
     wait_rows();
     ev = row(t + 2);
@@ -593,12 +598,10 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
     __builtin_amdgcn_sched_barrier(0);
     flip_off(c1);
     body(t + 6, ev);
-    if (q + 1 == groups) {
-      wait_rows();
-      flip_off(c0);
-      body(t + 7, od);
-      break;
-    }
+  };
+  for (uint32_t q = 0; q + 1 < groups; ++q) {
+    six(q);
+    const uint32_t t = 8 * q;
     wait_rows();
     const uint32_t t8 = t + 8;
     const int l8 = __builtin_ctz(t8);
@@ -619,6 +622,10 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
       if (g < thr) retune(g);
     }
   }
+  six(groups - 1);
+  wait_rows();
+  flip_off(c0);
+  body(8 * (groups - 1) + 7, od);
 }
 
 template <class E, bool kHalf>
