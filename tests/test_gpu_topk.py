@@ -198,7 +198,7 @@ def test_forced_small_candidate_list_is_uncertain(gpu_lib):
     _assert_same(e, m, E, M)
 
 
-@pytest.mark.parametrize("outer,unit", [(0, 0), (2, 3), (6, 12), (12, 1), (20, 0)])
+@pytest.mark.parametrize("outer,unit", [(0, 0), (2, 3), (3, 2), (4, 5), (5, 0), (6, 12), (12, 1), (20, 0)])
 def test_plan_invariance(gpu_lib, outer, unit):
     # Sec. 3.1: any split into independent sub-walks gives the same result.
     from paper_2310_19373_amd import _lib
@@ -211,6 +211,8 @@ def test_plan_invariance(gpu_lib, outer, unit):
     _lib.set_tuning(_lib.TUNE_SINGLE_UNIT_BITS, unit)
     try:
         e, m = _solve(Q, 6)
+        _assert_same(e, m, E, M)
+        e, m = _solve(Q.astype(np.float64), 6)  # float64 Q of the same values
         _assert_same(e, m, E, M)
         e, m = _solve(Qi, 6)
         _assert_same(e, m, Ei, Mi)
