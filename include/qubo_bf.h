@@ -227,7 +227,9 @@ const char* qubo_version(void);
  *                                 (upper bound, default 14; n <= 32 reserves
  *                                 min(11, max(8, n - 18)), 12 in place of 11
  *                                 and 13 in place of 14 for walks other than
- *                                 the float32 half screen)
+ *                                 the float32 half screen; int32 Q under the
+ *                                 half screen reserves 12 at n = 32..35 and 13
+ *                                 from n = 36)
  *   QUBO_TUNE_BATCHED_OUTER_BITS  max outer bits per work unit, batched / logZ
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
  *                                 (0, the default, reads back as 0 and means

@@ -259,10 +259,14 @@ PlanParams single_params(int kp, int n, int dt) {
   // Measured with the float32 walk's half screen: n=24 -> 8, n=28 -> 10,
   // n=30..32 -> 11, n=33..36 -> 14 (n=38 is flat; n=40 reaches 16 unit bits
   // either way).  The walks with a costlier step (the float32 and int32
-  // screens) do best with one bit fewer: n=32 -> 12, n=34 -> 13.
+  // screens) do best with one bit fewer: n=32 -> 12, n=34 -> 13.  int32 Q
+  // under the half screen (the int16 screen where its values fit) gains from
+  // more, shorter units from n = 32: 12 up to n = 35 (n=32: 0.31 ms per call
+  // against 0.35 at 11; n=33: 0.42 against 0.50 at 14), 13 from n = 36.
   const bool half = t.half_screen > 0;
   const int mid_cap = half ? 11 : 12, big = half ? 14 : 13;
-  const int want = n >= 33 ? big : (n - 18 > mid_cap ? mid_cap : (n - 18 > 8 ? n - 18 : 8));
+  int want = n >= 33 ? big : (n - 18 > mid_cap ? mid_cap : (n - 18 > 8 ? n - 18 : 8));
+  if (half && dt == kDtI32 && n >= 32) want = n >= 36 ? 13 : 12;
   pp.ub_min = clampi(t.single_unit < want ? t.single_unit : want, 0, 62);
   pp.inner = kInner;
   pp.kprime = kp;
