@@ -308,14 +308,29 @@ __device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
 }
 
 // The same for a float32 row, 16-byte LDS loads (np is a multiple of 4 and
-// rows start 16-byte aligned) and 32-bit halves of x.
+// rows start 16-byte aligned), summed in the same order as field().
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float field_f4(const float* row, int np, uint64_t x) {
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-  for (int j = 0; j < np; j += 4) {
+  int j = 0;
+  // 16 entries per step: four loads in flight before their sums (one wave per
+  // SIMD runs this chain, so the LDS latency is not hidden by other waves)
+  for (; j + 16 <= np; j += 16) {
+    f32x4_t r[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r[c] = *(const f32x4_t*)(row + j + 4 * c);
+    const uint32_t bits = (uint32_t)(x >> j);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      a0 += ((bits >> (4 * c)) & 1u) ? r[c].x : 0.f;
+      a1 += ((bits >> (4 * c)) & 2u) ? r[c].y : 0.f;
+      a2 += ((bits >> (4 * c)) & 4u) ? r[c].z : 0.f;
+      a3 += ((bits >> (4 * c)) & 8u) ? r[c].w : 0.f;
+    }
+  }
+  for (; j < np; j += 4) {
     const f32x4_t r = *(const f32x4_t*)(row + j);
-    const uint32_t bits = j < 32 ? lo >> j : hi >> (j - 32);
+    const uint32_t bits = (uint32_t)(x >> j);
     a0 += (bits & 1u) ? r.x : 0.f;
     a1 += (bits & 2u) ? r.y : 0.f;
     a2 += (bits & 4u) ? r.z : 0.f;
