@@ -93,6 +93,26 @@ size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt);
 int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
                   int32_t* status, void* ws, size_t ws_bytes, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: qubo_bf_solve
+ * without a workspace argument.  The workspace is a library-owned static
+ * device array of QUBO_NOALLOC_SCRATCH_BYTES (16 MiB), one per GPU, held until
+ * the process ends; it covers every single solve (n <= 63, any k, any tuning).
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); on its first call on a device it looks up that device's copy of
+ * the array (hipGetSymbolAddress) and keeps the address.
+ *   Arguments, outputs, status and return codes as qubo_bf_solve; a
+ *   workspace need above the array's size returns QUBO_ERR_WORKSPACE.
+ * Every call on one GPU shares that GPU's array, and the array keeps the last
+ * call's contents (each call resets what it reads before reading it): calls
+ * that overlap in time on one GPU -- from other threads, or on other streams
+ * without ordering -- race and must not be issued.
+ */
+#define QUBO_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int qubo_bf_solve_noalloc(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies,
+                          uint64_t* masks, int32_t* status, void* hip_stream);
+
 /* Workspace bytes for qubo_bf_solve_batched with every n_b <= nmax. */
 size_t qubo_bf_batched_workspace_size(int batch, int nmax, int k, qubo_dtype dt);
 

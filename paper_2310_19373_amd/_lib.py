@@ -38,11 +38,15 @@ TUNE_LOGZ_FACTORED = 9
 TUNE_SEED_SWEEPS = 10
 TUNE_HALF_SCREEN = 11
 
+# size of the static workspace array of qubo_bf_solve_noalloc (QUBO_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
 # Every symbol include/qubo_bf.h declares: name -> (restype, argtypes)
 _vp, _sz, _i, _i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64
 SIGNATURES = {
     "qubo_bf_workspace_size": (_sz, [_i, _i, _i]),
     "qubo_bf_solve": (_i, [_vp, _i, _i64, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qubo_bf_solve_noalloc": (_i, [_vp, _i, _i64, _i, _i, _vp, _vp, _vp, _vp]),
     "qubo_bf_batched_workspace_size": (_sz, [_i, _i, _i, _i]),
     "qubo_bf_range_workspace_size": (_sz, [_i, _i, _i, _i]),
     "qubo_bf_solve_range": (_i, [_vp, _i, _i64, _i, _i, _i, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),

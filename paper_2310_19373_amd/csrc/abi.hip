@@ -337,7 +337,7 @@ PlanParams with_dt(PlanParams pp, qubo_dtype dt) {
 // Enqueue plan -> prep -> tables -> walk -> finalize for a top-k call.
 int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const int32_t* ns, int n_single,
              int dt, int k, PlanParams pp, int64_t units_hint, int64_t steps_hint, void* energies,
-             uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s) {
+             uint64_t* masks, int32_t* status, int fin_waves, hipStream_t s, bool prof = true) {
   Views v = v0;
   // float32, float64 and int64 Q screen blocks in packed float16 (the step
   // tables then hold HalfRow rows, 64 of the 256 bytes a float32 row takes);
@@ -361,11 +361,45 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
   // planner's seed_fix).
   const bool seed = ns != nullptr || n_single >= (dt_exact(dt) ? 19 : 15);
   HIPCHK(launch_prep_walk(v, dt, pp.inner, steps_hint, seed, s));
-  {
+  if (prof) {
     ProfScope ps("walk_topk", s);
+    HIPCHK(launch_walk_topk(v, dt, waves, s));
+  } else {
     HIPCHK(launch_walk_topk(v, dt, waves, s));
   }
   HIPCHK(launch_finalize_topk(v, Q, ldq, stride, dt, k, energies, masks, status, fin_waves, s));
+  return QUBO_OK;
+}
+
+// ------------------------------------------------- no-allocation solves
+//
+// Workspace of qubo_bf_solve_noalloc: a library-owned device array.  Every GPU
+// the library runs on holds its own copy, at its own address, until the
+// process ends.  In host code the array's name is only a stand-in for the
+// device symbol, never a device address: the address comes from
+// hipGetSymbolAddress, once per device with that device current, and host
+// code uses only that pointer (kernel arguments, views of the workspace).
+constexpr size_t kScratchBytes = QUBO_NOALLOC_SCRATCH_BYTES;  // covers every single solve, n <= 63, k <= 64
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on
+// that device.  Returns QUBO_OK or QUBO_ERR_HIP.
+int scratch_ptr(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QUBO_ERR_HIP, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(QUBO_ERR_HIP, "hipGetSymbolAddress(scratch) returned null on device %d", dev);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return QUBO_OK;
 }
 
@@ -470,6 +504,28 @@ int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void*
   const SplitH sh = split_host(n, pp);
   return run_topk(v, Q, ldq, 0, nullptr, n, dt, k, pp, int64_t(1) << sh.tb, int64_t(1) << sh.no, energies,
                   masks, status, 16, (hipStream_t)hip_stream);
+}
+
+int qubo_bf_solve_noalloc(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies,
+                          uint64_t* masks, int32_t* status, void* hip_stream) {
+  if (!Q || !energies || !masks || !status) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
+  if (n < 1 || n > 63) return fail(QUBO_ERR_INVALID_ARG, "n=%d outside [1, 63]", n);
+  if (ldq < n) return fail(QUBO_ERR_INVALID_ARG, "ldq=%lld < n=%d", (long long)ldq, n);
+  if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+  const bool exact = dt_exact(dt);
+  if (int rc = check_k(k, exact)) return rc;
+  const int kp = kprime_for(k, exact);
+  const PlanParams pp = with_dt(single_params(kp, n, dt), dt);
+  const Layout L = make_layout(1, n, pp, 0, 0);
+  if (L.total > kScratchBytes)
+    return fail(QUBO_ERR_WORKSPACE, "n=%d, k=%d needs a %zu-byte workspace, above the %zu-byte static scratch", n, k,
+                L.total, kScratchBytes);
+  void* ws = nullptr;
+  if (int rc = scratch_ptr(&ws)) return rc;
+  const Views v = make_views(ws, L, 1, n);
+  const SplitH sh = split_host(n, pp);
+  return run_topk(v, Q, ldq, 0, nullptr, n, dt, k, pp, int64_t(1) << sh.tb, int64_t(1) << sh.no, energies,
+                  masks, status, 16, (hipStream_t)hip_stream, false);
 }
 
 static int check_range(int n, int p_bits, int64_t p_begin, int64_t p_end) {

@@ -131,3 +131,25 @@ def test_sample_argument_checks():
     assert L.qubo_logz_sample(*args(nmax=33)) == -1
     assert L.qubo_logz_sample(*args(batch=0)) == -1
     assert L.qubo_logz_sample(*args(ws_bytes=64)) == -3
+
+
+def test_noalloc_scratch_covers_every_single_solve():
+    # the static workspace array of qubo_bf_solve_noalloc holds the workspace
+    # of every single solve at the default tuning
+    L = _lib.lib()
+    for dt, kmax in ((0, 56), (1, 64), (2, 56), (3, 64)):
+        for n in range(1, 64):
+            for k in (1, 16, kmax):
+                assert 0 < L.qubo_bf_workspace_size(n, k, dt) <= _lib.NOALLOC_SCRATCH_BYTES, (dt, n, k)
+
+
+@pytest.mark.parametrize("case", [dict(Q=None), dict(n=0), dict(n=64), dict(ldq=5), dict(dt=4), dict(k=0),
+                                  dict(k=57), dict(status=None), dict(masks=None)])
+def test_noalloc_rejects_before_any_hip_call(case):
+    L = _lib.lib()
+    a = dict(Q=FAKE, n=10, ldq=10, dt=0, k=4, en=FAKE, masks=FAKE, status=FAKE, stream=None)
+    a.update(case)
+    rc = L.qubo_bf_solve_noalloc(a["Q"], a["n"], a["ldq"], a["dt"], a["k"], a["en"], a["masks"], a["status"],
+                                 a["stream"])
+    assert rc == -1
+    assert L.qubo_last_error()
