@@ -32,21 +32,28 @@
  *   - Calls that share a workspace must not overlap in time.
  *   - qubo_last_error() describes the last non-OK return of the calling thread.
  *
- * Float semantics: float32 Q is enumerated with float32 table arithmetic; the
- * K' >= k best candidates are rescored in float64 in a fixed order (row i
- * ascending: Q_ii, then Q_ij for set j > i in ascending j; rows summed in
- * ascending i) and selected by (float64 energy, mask).  A certificate proves
- * that no state outside the candidates can rank among the k best; when it fails
- * the outputs are still written and `status` is QUBO_ERR_UNCERTAIN.
- * Integer semantics: int32 Q, exact int32 walk (requires sum_{i<=j} |Q_ij| <=
- * 2^28, else status QUBO_ERR_RANGE), int64 energies, bit-exact results.
- * Wide types: float64 Q (QUBO_F64) and int64 Q (QUBO_I64) are enumerated in
- * float64 arithmetic (about twice the time of the float32 walk).  QUBO_F64
- * rescores in float64 and certifies like QUBO_F32 with a bound of
- * 2^-36 sum |Q_ij| (0 for integer-valued Q with sum |Q_ij| <= 2^50);
- * QUBO_I64 is exact and bit-exact for sum |Q_ij| <= 2^50 (else status
- * QUBO_ERR_RANGE), with int64 energies -- the path for integer Q whose sum
- * exceeds the int32 walk's 2^28.
+ * Float semantics (float32 and float64 Q): every block of 64 states is
+ * screened against the current threshold -- by default in packed float16 on
+ * scaled values, with a margin that keeps every block a float32 screen would
+ * keep (QUBO_TUNE_HALF_SCREEN = -1 selects the float32 / float64 screens;
+ * results are identical) -- and the blocks that pass are replayed with
+ * float64 keys.  The K' >= k best candidates are rescored in float64 in a
+ * fixed order (row i ascending: Q_ii, then Q_ij for set j > i in ascending j;
+ * rows summed in ascending i) and selected by (float64 energy, mask).  A
+ * certificate proves that no state outside the candidates can rank among the
+ * k best: every discarded state's exact value is at least the K'-th key
+ * minus eps, eps = 3 * 2^-24 * R_I + 2^-36 * sum |Q_ij| for float32 Q (R_I:
+ * sum |Q_ij| over the six lowest rows) and 2^-36 * sum |Q_ij| for float64 Q,
+ * 0 for integer-valued Q within the exact range (sum |Q_ij| <= 2^24 float32,
+ * 2^50 float64).  When it fails the outputs are still written and `status`
+ * is QUBO_ERR_UNCERTAIN (qubo_bf_solve_kp with kprime = 64 gives it more
+ * room).
+ * Integer semantics: int32 and int64 Q, int64 energies, bit-exact results.
+ * int32 Q screens in exact int16 where the six lowest rows allow it, else in
+ * int32; an instance with sum |Q_ij| > 2^28 is walked on float64 tables,
+ * still exactly (every int32 Q has sum |Q_ij| < 2^50).  int64 Q is walked on
+ * float64 tables, exact for sum |Q_ij| <= 2^50 (else status QUBO_ERR_RANGE).
+ * Floating-point and integer walks take about the same time per state.
  */
 #ifndef QUBO_BF_H
 #define QUBO_BF_H
@@ -58,7 +65,17 @@
 extern "C" {
 #endif
 
-typedef enum { QUBO_F32 = 0, QUBO_I32 = 1, QUBO_F64 = 2, QUBO_I64 = 3 } qubo_dtype;
+/* The two range enumerators make every int a valid value of the type, so
+ * that an unknown value passed from C is rejected (QUBO_ERR_INVALID_ARG)
+ * rather than being undefined in the C++ implementation. */
+typedef enum {
+  QUBO_F32 = 0,
+  QUBO_I32 = 1,
+  QUBO_F64 = 2,
+  QUBO_I64 = 3,
+  QUBO_DTYPE_RANGE_LO_ = -0x7fffffff - 1,
+  QUBO_DTYPE_RANGE_HI_ = 0x7fffffff
+} qubo_dtype;
 
 enum {
   QUBO_OK = 0,
@@ -67,7 +84,7 @@ enum {
   QUBO_ERR_WORKSPACE = -3,   /* ws_bytes smaller than the workspace query */
   QUBO_ERR_HIP = -4,         /* a HIP launch or runtime call failed */
   QUBO_ERR_UNCERTAIN = -5,   /* float certificate failed (device status) */
-  QUBO_ERR_RANGE = -6,       /* integer Q whose sum |Q_ij| exceeds its walk's bound (device status) */
+  QUBO_ERR_RANGE = -6,       /* int64 Q whose sum |Q_ij| exceeds 2^50 (device status) */
   QUBO_ERR_OVERFLOW = -7     /* internal slot overflow (device status; a bug) */
 };
 
@@ -92,6 +109,20 @@ size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt);
  */
 int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
                   int32_t* status, void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * qubo_bf_solve with the length K' of the candidate lists given: kprime in
+ * [k, 64], or 0 for the default (max(2k, k + 8) capped at 64 for float Q, k
+ * for integer Q).  A longer list gives the float certificate more room above
+ * the k-th value (a solve whose status was QUBO_ERR_UNCERTAIN can be repeated
+ * with kprime = 64), at a larger workspace: qubo_bf_workspace_size_kp, 0 for
+ * invalid arguments.  The results of a certified solve do not depend on K'.
+ * Unlike the process-wide QUBO_TUNE_KPRIME knob this affects only the call.
+ * Returns as qubo_bf_solve (QUBO_ERR_INVALID_ARG for a bad kprime).
+ */
+size_t qubo_bf_workspace_size_kp(int n, int k, int kprime, qubo_dtype dt);
+int qubo_bf_solve_kp(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int kprime, void* energies,
+                     uint64_t* masks, int32_t* status, void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
  * For callers that cannot allocate device memory -- code under HIP graph
@@ -145,7 +176,7 @@ size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits);
  * the result is exact (and, for float Q, certified) for that range, so the
  * k lowest of the union of the results of disjoint ranges (qubo_bf_merge_topk)
  * is the result of qubo_bf_solve.
- *   p_bits   1 .. min(20, n - 12)
+ *   p_bits   1 .. n - 12 (a range of one prefix holds 2^(n - p_bits) masks)
  *   p_begin, p_end   0 <= p_begin < p_end <= 2^p_bits
  */
 int qubo_bf_solve_range(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int p_bits, int64_t p_begin,

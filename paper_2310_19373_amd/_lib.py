@@ -10,7 +10,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqubo_bf.so")
+# QUBO_BF_LIB: another build of the same library (the sanitizer run of the CPU tests)
+LIB_PATH = os.environ.get("QUBO_BF_LIB") or os.path.join(_HERE, "libqubo_bf.so")
 
 QUBO_F32 = 0
 QUBO_I32 = 1
@@ -46,6 +47,8 @@ _vp, _sz, _i, _i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_in
 SIGNATURES = {
     "qubo_bf_workspace_size": (_sz, [_i, _i, _i]),
     "qubo_bf_solve": (_i, [_vp, _i, _i64, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qubo_bf_workspace_size_kp": (_sz, [_i, _i, _i, _i]),
+    "qubo_bf_solve_kp": (_i, [_vp, _i, _i64, _i, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qubo_bf_solve_noalloc": (_i, [_vp, _i, _i64, _i, _i, _vp, _vp, _vp, _vp]),
     "qubo_bf_batched_workspace_size": (_sz, [_i, _i, _i, _i]),
     "qubo_bf_range_workspace_size": (_sz, [_i, _i, _i, _i]),

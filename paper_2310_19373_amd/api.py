@@ -31,7 +31,7 @@ _STATUS = {
     _lib.QUBO_ERR_INVALID_ARG: "invalid instance size",
     _lib.QUBO_ERR_NONFINITE: "Q or beta holds inf or NaN",
     _lib.QUBO_ERR_UNCERTAIN: "float certificate failed",
-    _lib.QUBO_ERR_RANGE: "integer Q with sum |Q_ij| beyond the walk's exact range (2^28 int32, 2^50 int64)",
+    _lib.QUBO_ERR_RANGE: "int64 Q with sum |Q_ij| beyond the exact range (2^50)",
     _lib.QUBO_ERR_OVERFLOW: "internal candidate slot overflow",
 }
 
@@ -82,15 +82,15 @@ def _check_upper(Q: torch.Tensor):
         raise ValueError("Q must be upper triangular (entries below the diagonal are nonzero)")
 
 
-def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = True):
+def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = True, kprime: int = 0):
     """The k lowest states of f_Q(x) = x^T Q x over x in {0,1}^n.
 
     Q: (n, n) float32, int32, float64 or int64 tensor/array, upper triangular.
     Returns (energies, masks) on Q's GPU: float64 (float Q) or int64 (int Q),
     and int64 tensors holding the uint64 masks (bit i = x_i), ascending by
     (energy, mask).  Slots beyond 2^n hold +inf / INT64_MAX and mask -1.
-    int32 Q whose sum |Q_ij| exceeds the int32 walk's 2^28 is solved again as
-    int64 (the exact float64 walk).
+    kprime: candidate list length (0: the library's default); a float solve
+    whose certificate fails is repeated once with 64 when retry_uncertain.
     """
     Qd = _as_device(Q)
     if Qd.ndim != 2 or Qd.shape[0] != Qd.shape[1]:
@@ -100,32 +100,23 @@ def solve(Q, k: int = 1, *, check_lower: bool = True, retry_uncertain: bool = Tr
     n = Qd.shape[0]
     dt = _qdtype(Qd)
     L = _lib.lib()
-    ws_bytes = L.qubo_bf_workspace_size(n, k, dt)
+    ws_bytes = L.qubo_bf_workspace_size_kp(n, k, kprime, dt)
     if ws_bytes == 0:
-        raise ValueError(f"invalid arguments n={n}, k={k}: {_lib.last_error()}")
+        raise ValueError(f"invalid arguments n={n}, k={k}, kprime={kprime}: {_lib.last_error()}")
     dev = Qd.device
     with torch.cuda.device(dev):
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
         en = torch.empty(k, dtype=_energy_dtype(dt), device=dev)
         masks = torch.empty(k, dtype=torch.int64, device=dev)
         status = torch.empty(1, dtype=torch.int32, device=dev)
-        _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, n, dt, k, en.data_ptr(), masks.data_ptr(), status.data_ptr(),
-                                   ws.data_ptr(), ws_bytes, _stream(dev)))
+        _lib.check(L.qubo_bf_solve_kp(Qd.data_ptr(), n, n, dt, k, kprime, en.data_ptr(), masks.data_ptr(),
+                                      status.data_ptr(), ws.data_ptr(), ws_bytes, _stream(dev)))
         try:
             _raise_status(status)
         except UncertainError:
-            if not retry_uncertain or dt not in (_lib.QUBO_F32, _lib.QUBO_F64):
+            if not retry_uncertain or dt not in (_lib.QUBO_F32, _lib.QUBO_F64) or kprime == 64:
                 raise
-            old = _lib.get_tuning(_lib.TUNE_KPRIME)
-            _lib.set_tuning(_lib.TUNE_KPRIME, 64)
-            try:
-                return solve(Qd, k, check_lower=False, retry_uncertain=False)
-            finally:
-                _lib.set_tuning(_lib.TUNE_KPRIME, old)
-        except QuboError as e:
-            if e.code != _lib.QUBO_ERR_RANGE or dt != _lib.QUBO_I32:
-                raise
-            return solve(Qd.to(torch.int64), k, check_lower=False)
+            return solve(Qd, k, check_lower=False, retry_uncertain=False, kprime=64)
     return en, masks
 
 
@@ -225,9 +216,20 @@ class BatchedSolver:
     ``run()`` enqueues the library's launch sequence; with ``graph=True`` the
     sequence is captured once into a HIP graph (no allocation, no host sync,
     no memset nodes inside) and later calls replay it.
+
+    ``autotune=True``: the first ``run()`` picks the launch shape (outer bits
+    per work unit, waves per CU, queue chunk) for the loaded batch with
+    ``autotune.tune_batched`` -- or takes it from ``tune_cache`` (a JSON file
+    keyed by the batch's size histogram) when it holds this workload -- and
+    the solver then enqueues under that shape: with ``graph=True`` it is
+    captured into the graph, else it is set around each enqueue.  The
+    library's tuning knobs are process-wide; they are restored after each
+    use, so other calls keep their own settings (calls from other threads
+    while a solver enqueues would see the solver's shape).
     """
 
-    def __init__(self, batch: int, nmax: int, k: int = 1, dtype=torch.float32, device=None, graph: bool = False):
+    def __init__(self, batch: int, nmax: int, k: int = 1, dtype=torch.float32, device=None, graph: bool = False,
+                 autotune: bool = False, tune_cache: str | None = None):
         self.batch, self.nmax, self.k = batch, nmax, k
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.dt = _qdtype(dtype)
@@ -244,13 +246,52 @@ class BatchedSolver:
         self.status = torch.empty(batch, dtype=torch.int32, device=d)
         self.use_graph = graph
         self.graph = None
+        self.autotune, self.tune_cache = autotune, tune_cache
+        self.setting = None       # the tuned launch shape (knob name -> value), once tuned
+        self.tune_result = None   # autotune.TuneResult when this solver ran the search
 
     def load(self, Qpad, ns):
         self.Q.copy_(_as_device(Qpad, self.Q.dtype, self.device))
         self.ns.copy_(_as_device(ns, torch.int32, self.device))
 
+    def _tune(self):
+        from . import autotune as at
+
+        names = list(at.BATCHED_SPACE)
+        sig = at.batched_signature(self.ns.cpu().numpy(), self.k, at._DT_NAMES[self.dt],
+                                   torch.cuda.get_device_name(self.device))
+        with at.keep_tuning(names):
+            best = at.load_cached(self.tune_cache, sig) if self.tune_cache else None
+            if best is None:
+                self.tune_result = at.tune_batched(self.Q, self.ns, self.k, apply_best=False, cache=self.tune_cache)
+                best = self.tune_result.best
+        self.use_setting(best)
+
+    def use_setting(self, setting: dict):
+        """Enqueue under this launch shape from now on (knob name -> value,
+        as autotune.BATCHED_SPACE); resizes the workspace if it needs to."""
+        from . import autotune as at
+
+        self.setting = dict(setting)
+        with at.keep_tuning(list(self.setting)):
+            at.apply(self.setting)
+            nbytes = _lib.lib().qubo_bf_batched_workspace_size(self.batch, self.nmax, self.k, self.dt)
+        if nbytes != self.ws_bytes:
+            self.ws_bytes = nbytes
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.graph = None
+
     def _enqueue(self):
         L = _lib.lib()
+        if self.setting is not None:
+            from . import autotune as at
+
+            with at.keep_tuning(list(self.setting)):
+                at.apply(self.setting)
+                return self._enqueue_now(L)
+        return self._enqueue_now(L)
+
+    def _enqueue_now(self, L):
         _lib.check(L.qubo_bf_solve_batched(self.batch, self.Q.data_ptr(), self.nmax, self.ns.data_ptr(), self.dt,
                                            self.k, self.energies.data_ptr(), self.masks.data_ptr(),
                                            self.status.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
@@ -258,6 +299,8 @@ class BatchedSolver:
 
     def run(self):
         with torch.cuda.device(self.device):
+            if self.autotune and self.setting is None:
+                self._tune()
             if not self.use_graph:
                 self._enqueue()
                 return
@@ -280,7 +323,9 @@ class BatchedSolver:
 
 
 def solve_batched(Qpad, ns, k: int = 1, *, check_lower: bool = True):
-    """Independent k-lowest solves of many QUBOs.
+    """Independent k-lowest solves of many QUBOs, one launch sequence at the
+    current launch shape (for repeated solves of one shape, a BatchedSolver
+    with graph=True and autotune=True).
 
     Qpad: (batch, nmax, nmax) float32/int32/float64/int64, instance b in Qpad[b, :ns[b], :ns[b]].
     Returns (energies [batch, k], masks [batch, k]) on the GPU.
@@ -359,13 +404,14 @@ class LogZ(torch.autograd.Function):
         return gq, gb, None
 
 
-def logz(Q, beta, ns=None):
+def logz(Q, beta, ns=None, *, check_lower: bool = True):
     """Exact log-partition function log sum_x exp(-beta f_Q(x)), differentiable.
 
     Q: (n, n) or (batch, nmax, nmax) float32 tensor (CUDA or CPU, upper
-    triangular); beta: float or (batch,) tensor; ns: instance sizes for a
-    padded batch (default: all nmax).  Returns float64: a 0-d tensor for a
-    single Q, else (batch,).
+    triangular: a nonzero lower triangle raises ValueError unless check_lower
+    is False, in which case it is ignored); beta: float or (batch,) tensor;
+    ns: instance sizes for a padded batch (default: all nmax).  Returns
+    float64: a 0-d tensor for a single Q, else (batch,).
     """
     single = False
     if not isinstance(Q, torch.Tensor):
@@ -377,6 +423,8 @@ def logz(Q, beta, ns=None):
         raise TypeError("Q must be float32")
     if not Q.is_cuda:
         Q = Q.to("cuda")
+    if check_lower:
+        _check_upper(Q.detach())
     dev = Q.device
     batch, nmax = Q.shape[0], Q.shape[1]
     if not isinstance(beta, torch.Tensor):

@@ -28,6 +28,8 @@ import numpy as np
 
 from . import _lib
 
+_DT_NAMES = {_lib.QUBO_F32: "f32", _lib.QUBO_I32: "i32", _lib.QUBO_F64: "f64", _lib.QUBO_I64: "i64"}
+
 # knob name -> C ABI identifier (qubo_bf_set_tuning)
 KNOBS = {
     "single_outer": _lib.TUNE_SINGLE_OUTER_BITS,
@@ -184,13 +186,13 @@ def tune_batched(Qpad, ns, k: int = 1, *, space: dict | None = None, reps: int =
     setting's."""
     import torch
 
-    from .api import BatchedSolver, _as_device
+    from .api import BatchedSolver, _as_device, _qdtype
 
     space = BATCHED_SPACE if space is None else space
     Qd = _as_device(Qpad)
     nsd = _as_device(ns, torch.int32, Qd.device)
     batch, nmax = Qd.shape[0], Qd.shape[1]
-    dtype = "f32" if Qd.dtype == torch.float32 else "i32"
+    dtype = _DT_NAMES[_qdtype(Qd)]
     sig = batched_signature(nsd.cpu().numpy(), k, dtype, torch.cuda.get_device_name(Qd.device))
     names = list(space)
     ref = {}
@@ -226,15 +228,15 @@ def tune_single(Q, k: int = 1, *, space: dict | None = None, reps: int = 3, warm
     """The same search for qubo_bf_solve on one instance."""
     import torch
 
-    from .api import _as_device, _stream
+    from .api import _as_device, _energy_dtype, _qdtype, _stream
 
     space = SINGLE_SPACE if space is None else space
     Qd = _as_device(Q)
     n = Qd.shape[0]
-    dt = _lib.QUBO_F32 if Qd.dtype == torch.float32 else _lib.QUBO_I32
+    dt = _qdtype(Qd)
     L = _lib.lib()
     d = Qd.device
-    en = torch.empty(k, dtype=torch.float64 if dt == _lib.QUBO_F32 else torch.int64, device=d)
+    en = torch.empty(k, dtype=_energy_dtype(dt), device=d)
     mk = torch.empty(k, dtype=torch.int64, device=d)
     st = torch.empty(1, dtype=torch.int32, device=d)
     names = list(space)
@@ -263,7 +265,7 @@ def tune_single(Q, k: int = 1, *, space: dict | None = None, reps: int = 3, warm
         best, best_ms, trials = coordinate_descent(space, start, evaluate, rounds)
     if apply_best:
         apply(best)
-    sig = {"kind": "single", "n": int(n), "k": int(k), "dtype": "f32" if dt == _lib.QUBO_F32 else "i32",
+    sig = {"kind": "single", "n": int(n), "k": int(k), "dtype": _DT_NAMES[dt],
            "device": torch.cuda.get_device_name(d)}
     return TuneResult(best=best, ms=best_ms, start=start, start_ms=trials[0][1], signature=sig,
                       trials=[(s, c, "rejected" if c is None else "") for s, c in trials])

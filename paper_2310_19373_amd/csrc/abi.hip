@@ -480,22 +480,41 @@ int qubo_prof_collect(const char* name, double* total_ms, int64_t* launches) {
   return QUBO_OK;
 }
 
-size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt) {
+// Candidate list length of a single solve: kprime (k .. 64) when given,
+// else the default for k; -1 (with the error set) for a bad kprime.
+static int kprime_arg(int k, int kprime, bool exact) {
+  if (kprime == 0) return kprime_for(k, exact);
+  if (kprime < k || kprime > kMaxKPrime)
+    return fail(QUBO_ERR_INVALID_ARG, "kprime=%d outside [k=%d, %d]", kprime, k, kMaxKPrime), -1;
+  return kprime;
+}
+
+size_t qubo_bf_workspace_size_kp(int n, int k, int kprime, qubo_dtype dt) {
   if (n < 1 || n > 63 || !valid_dtype(dt)) return 0;
   const bool exact = dt_exact(dt);
   if (check_k(k, exact) != QUBO_OK) return 0;
-  return make_layout(1, n, with_dt(single_params(kprime_for(k, exact), n, dt), dt), 0, 0).total;
+  const int kp = kprime_arg(k, kprime, exact);
+  if (kp < 0) return 0;
+  return make_layout(1, n, with_dt(single_params(kp, n, dt), dt), 0, 0).total;
 }
+
+size_t qubo_bf_workspace_size(int n, int k, qubo_dtype dt) { return qubo_bf_workspace_size_kp(n, k, 0, dt); }
 
 int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void* energies, uint64_t* masks,
                   int32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
+  return qubo_bf_solve_kp(Q, n, ldq, dt, k, 0, energies, masks, status, ws, ws_bytes, hip_stream);
+}
+
+int qubo_bf_solve_kp(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, int kprime, void* energies,
+                     uint64_t* masks, int32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
   if (!Q || !energies || !masks || !status || !ws) return fail(QUBO_ERR_INVALID_ARG, "null pointer argument");
   if (n < 1 || n > 63) return fail(QUBO_ERR_INVALID_ARG, "n=%d outside [1, 63]", n);
   if (ldq < n) return fail(QUBO_ERR_INVALID_ARG, "ldq=%lld < n=%d", (long long)ldq, n);
   if (!valid_dtype(dt)) return fail(QUBO_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
   const bool exact = dt_exact(dt);
   if (int rc = check_k(k, exact)) return rc;
-  const int kp = kprime_for(k, exact);
+  const int kp = kprime_arg(k, kprime, exact);
+  if (kp < 0) return QUBO_ERR_INVALID_ARG;
   const PlanParams pp = with_dt(single_params(kp, n, dt), dt);
   const Layout L = make_layout(1, n, pp, 0, 0);
   if (ws_bytes < L.total)
@@ -529,8 +548,8 @@ int qubo_bf_solve_noalloc(const void* Q, int n, int64_t ldq, qubo_dtype dt, int 
 }
 
 static int check_range(int n, int p_bits, int64_t p_begin, int64_t p_end) {
-  if (p_bits < 1 || p_bits > 20 || p_bits > n - 12)
-    return fail(QUBO_ERR_INVALID_ARG, "p_bits=%d outside [1, min(20, n - 12)] for n=%d", p_bits, n);
+  if (p_bits < 1 || p_bits > n - 12)
+    return fail(QUBO_ERR_INVALID_ARG, "p_bits=%d outside [1, n - 12] for n=%d", p_bits, n);
   if (p_begin < 0 || p_end <= p_begin || p_end > (int64_t(1) << p_bits))
     return fail(QUBO_ERR_INVALID_ARG, "prefix range [%lld, %lld) outside [0, 2^%d)", (long long)p_begin,
                 (long long)p_end, p_bits);
@@ -546,7 +565,7 @@ static PlanParams range_params(int kp, int n, int dt, int p_bits, int64_t p_begi
 }
 
 size_t qubo_bf_range_workspace_size(int n, int k, qubo_dtype dt, int p_bits) {
-  if (n < 1 || n > 63 || !valid_dtype(dt) || p_bits < 1 || p_bits > 20 || p_bits > n - 12) return 0;
+  if (n < 1 || n > 63 || !valid_dtype(dt) || p_bits < 1 || p_bits > n - 12) return 0;
   const bool exact = dt_exact(dt);
   if (check_k(k, exact) != QUBO_OK) return 0;
   return make_layout(1, n, with_dt(range_params(kprime_for(k, exact), n, dt, p_bits, 0, 1), dt), 0, 0).total;

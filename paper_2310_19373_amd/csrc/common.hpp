@@ -75,6 +75,9 @@ struct Inst {
   int32_t kprime;           // candidate list length
   int32_t status;           // device-detected status, 0 = OK
   int32_t seed_fix;         // top bits the threshold seed keeps at the range's first prefix
+  int32_t wide;             // int32 Q beyond the int32 walk's range (sum |Q| > 2^28): the
+                            // instance's tables are float64 and it walks the half screen
+  int32_t pad_;
   int64_t units;            // 2^tb work units
   int64_t unit_begin;       // first global unit index
   int64_t local_off;        // tile value of the first unit (prefix-range solves; else 0)

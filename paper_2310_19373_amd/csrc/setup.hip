@@ -136,6 +136,28 @@ __device__ double absd(T x) {
   return fabs((double)x);
 }
 
+// Scale and margin of the half-precision screen.  Every screened value and
+// partial sum (C', Tb, Ta, C' + Tb, C' + Tb + Ta) is a partial sum of the inner
+// rows, so at most R_I in magnitude; scaled by hs = 2^s with R_I hs in
+// [2^12, 2^13) it stays far inside float16 range.  Five float16 roundings
+// (relative 2^-11 each) and the float32 ones put the screened value within
+// 5.01 * 2^-11 * R_I hs of hs times the float32 walk's; the threshold's
+// float64 / float32 roundings add at most 2^-22 R_I hs + 2^-52 sum|Q| hs;
+// float16 subnormals (or their flush) at most 5 * 2^-14.  hmargin covers all
+// of it, so every block the float32 screen would pass also passes the half
+// screen, and the float32 walk's error bound eps still holds.  (For the
+// float64 walk the same bound holds against its float64 screen, so its eps
+// and certificate are unchanged as well.)
+__device__ void set_half_screen(Inst* I, double rI, double sa) {
+  I->hscale = 1.0;
+  if (rI > 0.0 && isfinite(rI)) {
+    int e;
+    frexp(rI, &e);  // R_I in [2^(e-1), 2^e)
+    I->hscale = ldexp(1.0, 13 - e);
+  }
+  I->hmargin = I->hscale * (0x1p-8 * rI + 0x1p-50 * sa) + 0x1p-10;
+}
+
 // Qin: input element type; W: exact accumulation type of the tables; E: the
 // walk's element type (float32 / int32 / float64), which sets the error bound.
 template <class Qin, class W, class E>
@@ -155,19 +177,18 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
   if (I->status != 0) return;
   const int n = I->n, nmax = v.nmax, B = I->B;
   const Qin* Q = q + (int64_t)b * stride;
-  W* qs = (W*)v.qs + (int64_t)b * nmax * nmax;
   const double sgn = I->sign;
   double sabs = 0.0, rI = 0.0;
   int bad = 0, frac = 0;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {  // sums and validation over i <= j
     const int i = idx / n, j = idx % n;
-    const Qin val = (i <= j) ? Q[(int64_t)i * ldq + j] : Q[(int64_t)j * ldq + i];
+    if (j < i) continue;
+    const Qin val = Q[(int64_t)i * ldq + j];
     if constexpr (std::is_floating_point_v<Qin>) {
       if (!isfinite(val)) bad = 1;
-      if (i <= j && (double)val != trunc((double)val)) frac = 1;
+      if ((double)val != trunc((double)val)) frac = 1;
     }
-    qs[(int64_t)i * nmax + j] = (W)(sgn * (double)val);
-    if (i <= j) sabs += absd(val);
+    sabs += absd(val);
     if (i < B) rI += absd(val);
   }
   red_a[tid] = sabs;
@@ -184,6 +205,20 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
     }
     __syncthreads();
   }
+  // int32 Q beyond the int32 walk's exact range (sum |Q| > 2^28) takes
+  // float64 tables and the half-screen walk, exact for integer data with sum
+  // |Q| <= 2^50 -- which every int32 Q satisfies (at most 2016 entries of
+  // magnitude <= 2^31 for n <= 63)
+  bool wide = false;
+  if constexpr (std::is_same_v<E, int32_t>) wide = red_a[0] > (double)kIntSumLimit;
+  // the symmetric copy (S off the diagonal, d on it), sign applied
+  W* qs = (W*)v.qs + (int64_t)b * nmax * nmax;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    const Qin val = (i <= j) ? Q[(int64_t)i * ldq + j] : Q[(int64_t)j * ldq + i];
+    if (wide) ((double*)qs)[(int64_t)i * nmax + j] = sgn * (double)val;
+    else qs[(int64_t)i * nmax + j] = (W)(sgn * (double)val);
+  }
   // E_I(j) for the inner bits, straight from Eq. 1 restricted to bits < B.
   if (tid < (1 << inner)) {
     W e = 0;
@@ -194,20 +229,26 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
         if ((tid >> w) & 1) row += (W)(sgn * (double)Q[(int64_t)u * ldq + w]);
       e += row;
     }
-    ((W*)v.ei)[(int64_t)b * 64 + tid] = e;
+    if (wide) ((double*)v.ei)[(int64_t)b * 64 + tid] = (double)e;  // exact: |e| <= sum |Q|
+    else ((W*)v.ei)[(int64_t)b * 64 + tid] = e;
   }
   if (tid == 0) {
     const double sa = red_a[0];
     I->sumabs = sa;
     I->hscale = 1.0;
     I->hmargin = 0.0;
+    I->wide = wide ? 1 : 0;
     if constexpr (std::is_same_v<E, int32_t>) {
       I->big = sa + 1.0;
       I->eps = 0.0;
-      if (sa > (double)kIntSumLimit) I->status = kErrRange;
-      // int16 screen: C', Tb, Ta and their sums are partial sums of the
-      // inner rows, exact int16 values when R_I <= 32767
-      I->hscale = red_r[0] <= (double)kInt16Limit ? 1.0 : 0.0;
+      if (wide) {
+        if (sa > kWideSumLimit) I->status = kErrRange;  // cannot happen for n <= 63; kept as a guard
+        set_half_screen(I, red_r[0], sa);
+      } else {
+        // int16 screen: C', Tb, Ta and their sums are partial sums of the
+        // inner rows, exact int16 values when R_I <= 32767
+        I->hscale = red_r[0] <= (double)kInt16Limit ? 1.0 : 0.0;
+      }
     } else if constexpr (std::is_integral_v<Qin>) {
       // integer Q on the float64 walk: exact below kWideSumLimit
       I->big = sa + 1.0;
@@ -220,7 +261,11 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
       // with sum |Q| <= 2^50.
       I->big = sa * (1.0 + 1e-9) + 1.0;
       I->eps = 0x1p-36 * sa;
-      if (!red_frac[0] && sa <= kWideSumLimit) I->eps = 0.0;
+      if (!red_frac[0] && sa <= kWideSumLimit) {
+        // exact: integer thresholds keep every offset and key an integer
+        I->eps = 0.0;
+        I->big = sa + 1.0;
+      }
       if (red_bad[0]) I->status = kErrNonfinite;
     } else {
       I->big = sa * (1.0 + 1e-6) + 1.0;
@@ -232,30 +277,17 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
       // Integer-valued float Q with sum |Q| <= 2^24: every table value, sum and
       // key is an integer below 2^24 in magnitude, exact in float32 and float64,
       // so the walk is exact (eps = 0) and ties are resolved like the int path.
-      if (!red_frac[0] && sa <= 16777216.0) I->eps = 0.0;
+      // The threshold bound is then an integer as well: a fractional
+      // threshold would round the float64 offset Dp = thr - E_P (and the replay
+      // keys taken from it) by a lane-dependent amount, and equal energies
+      // would no longer compare equal.
+      if (!red_frac[0] && sa <= 16777216.0) {
+        I->eps = 0.0;
+        I->big = sa + 1.0;
+      }
       if (red_bad[0]) I->status = kErrNonfinite;
     }
-    if constexpr (!std::is_same_v<E, int32_t>) {
-      // Half-precision screen.  Every screened value and partial sum (C',
-      // Tb, Ta, C' + Tb, C' + Tb + Ta) is a partial sum of the inner rows, so
-      // at most R_I in magnitude; scaled by hs = 2^s with R_I hs in
-      // [2^12, 2^13) it stays far inside float16 range.  Five float16
-      // roundings (relative 2^-11 each) and the float32 ones put the screened
-      // value within 5.01 * 2^-11 * R_I hs of hs times the float32 walk's;
-      // the threshold's float64 / float32 roundings add at most
-      // 2^-22 R_I hs + 2^-52 sum|Q| hs; float16 subnormals (or their flush)
-      // at most 5 * 2^-14.  hmargin covers all of it, so every block the
-      // float32 screen would pass also passes the half screen, and the
-      // float32 walk's error bound eps still holds.
-      if (red_r[0] > 0.0 && isfinite(red_r[0])) {
-        int e;
-        frexp(red_r[0], &e);  // R_I in [2^(e-1), 2^e)
-        I->hscale = ldexp(1.0, 13 - e);
-      }
-      I->hmargin = I->hscale * (0x1p-8 * red_r[0] + 0x1p-50 * sa) + 0x1p-10;
-      // (For the float64 walk the same bound holds against its float64 screen,
-      // so its eps and certificate are unchanged as well.)
-    }
+    if constexpr (!std::is_same_v<E, int32_t>) set_half_screen(I, red_r[0], sa);
   }
 }
 
@@ -488,13 +520,18 @@ __device__ void seed_role(const Views& v, int b, unsigned char* seed_lds) {
   }
   const double vk = readlane_f64(lkey, kp - 1);
   if (lane == 0 && vk < __builtin_inf()) {
-    // float: the walk's filter error (eps) plus float64 rounding of the sums here
-    const double margin = std::is_same_v<W, double> ? I->eps + 1e-12 * I->sumabs : 0.0;
+    // float: the walk's filter error (eps) plus float64 rounding of the sums
+    // here.  Exact instances (eps = 0: integer data whose sums stay below
+    // 2^53) publish the value itself, an integer, so that the walk's offsets
+    // and replay keys stay exact and equal energies compare equal.
+    const double margin = (std::is_same_v<W, double> && I->eps > 0.0) ? I->eps + 1e-12 * I->sumabs : 0.0;
     v.gthr[b] = enc_key(vk + margin);
   }
 }
 
-template <class W, class E>
+// kWideI32: an int32 instance beyond the int32 walk's range (float64 W, float16
+// rows in the int32 layout's 256-byte step slots, whatever the screen knob).
+template <class W, class E, bool kWideI32 = false>
 __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigned char* lds) {
   // chunk: blockDim.x consecutive steps of instance b.  The entries the step
   // scalars need -- S(u, B+l) for inner u and S(B+l, B+l2) for outer l, l2 --
@@ -536,12 +573,14 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
     }
     const int64_t s = I->tab_off + t;
     v.eod[s] = (double)eo;
-    v.eoi[s] = (int32_t)(-eo);
     StepRec* r = &v.rec[s];
     r->eo = (double)eo;
 #pragma unroll
     for (int u = 0; u < 6; ++u) r->h[u] = (double)H[u];
-    r->neo = (int32_t)(-eo);
+    // -E_O as int32: read by the int32 walks only (|E_O| <= sum |Q| <= 2^28 there)
+    const int32_t neo = std::is_same_v<E, int32_t> ? (int32_t)(-eo) : 0;
+    v.eoi[s] = neo;
+    r->neo = neo;
     r->pad = 0;
     if constexpr (std::is_same_v<E, int32_t>) {
       if (v.h16 && I->hscale != 0.0) {
@@ -566,7 +605,7 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
       }
     }
     if constexpr (!std::is_same_v<E, int32_t>) {
-      if (v.h16) {
+      if (kWideI32 || v.h16) {
         // the half screen's row: Tb / Ta from the linear split of T'
         const double hs = I->hscale;
         auto h16 = [&](double x) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(x * hs)); };
@@ -587,12 +626,12 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
         hr.neo = 0;
         hr.pad0 = hr.pad1[0] = hr.pad1[1] = 0;
         hr.tau = (double)eo * hs - I->hmargin;
-        ((HalfRow*)v.tab)[s] = hr;
+        ((HalfRow*)v.tab)[kWideI32 ? s * kInt16RowStride : s] = hr;
       }
     }
   }
   if constexpr (!std::is_same_v<E, int32_t>) {
-    if (v.h16) return;  // the half screen reads HalfRow rows only
+    if (kWideI32 || v.h16) return;  // the half screen reads HalfRow rows only
   }
   if constexpr (std::is_same_v<E, int32_t>) {
     if (v.h16 && I->hscale != 0.0) return;  // the int16 screen reads HalfRow rows only
@@ -616,17 +655,28 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
 // instance; blockIdx.y = 0 the threshold seed (when seed_on), 1 the lane
 // table, 2 + c the step tables of chunk c.  The three only read what
 // prep_inst wrote, so their latencies overlap.
+template <class W, class E, bool kWideI32>
+__device__ void prep_walk_roles(const Views& v, int b, int role, int inner, int seed_on, unsigned char* lds) {
+  if (role == 0) {
+    if (seed_on) seed_role<W>(v, b, lds);
+  } else if (role == 1) {
+    if (threadIdx.x < kWave) lanes_role<W>(v, b, threadIdx.x);
+  } else {
+    tables_role<W, E, kWideI32>(v, b, role - 2, inner, lds);
+  }
+}
+
 template <class W, class E>
 __global__ void __launch_bounds__(kSeedThreads) prep_walk_kernel(Views v, int inner, int seed_on) {
   extern __shared__ __attribute__((aligned(16))) unsigned char prep_lds[];
   const int b = blockIdx.x, role = blockIdx.y;
-  if (role == 0) {
-    if (seed_on) seed_role<W>(v, b, prep_lds);
-  } else if (role == 1) {
-    if (threadIdx.x < kWave) lanes_role<W>(v, b, threadIdx.x);
-  } else {
-    tables_role<W, E>(v, b, role - 2, inner, prep_lds);
+  if constexpr (std::is_same_v<E, int32_t>) {
+    if (v.inst[b].wide) {  // float64 tables, half-screen rows (uniform over the block)
+      prep_walk_roles<double, float, true>(v, b, role, inner, seed_on, prep_lds);
+      return;
+    }
   }
+  prep_walk_roles<W, E, false>(v, b, role, inner, seed_on, prep_lds);
 }
 
 }  // namespace

@@ -313,6 +313,10 @@ __device__ __forceinline__ void wait_rows() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// kRowStride: HalfRow units between consecutive step rows (1: the float
+// layout; kInt16RowStride: an int32 instance beyond the int32 walk's range,
+// whose rows sit in the int32 layout's 256-byte step slots).
+template <int kRowStride = 1>
 __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU& I, uint64_t local, double& lkey,
                                               uint64_t& lmask, uint64_t& pub, double* myc, int lane) {
   const bool valid = lane < (1 << I.L);
@@ -337,13 +341,13 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
   double Dp = (thr - EP) * hs;  // the float32 walk's Dp, scaled
   const uint32_t steps = 1u << I.no;
   // the rows through the constant address space: scalar loads
-  const half_words_t rows = (half_words_t)((const HalfRow*)v.tab + I.tab_off);
+  const half_words_t rows = (half_words_t)((const HalfRow*)v.tab + I.tab_off * kRowStride);
   const double c0 = I.no > 0 ? myc[lane] * hs : 0.0;
   const double c1 = I.no > 1 ? myc[kWave + lane] * hs : 0.0;
   const double c2 = I.no > 2 ? myc[2 * kWave + lane] * hs : 0.0;
 
   auto row = [&](uint32_t t) -> HalfRow {
-    const half_words_t w = rows + (size_t)(t < steps ? t : steps - 1) * (sizeof(HalfRow) / 4);
+    const half_words_t w = rows + (size_t)(t < steps ? t : steps - 1) * (kRowStride * sizeof(HalfRow) / 4);
     HalfRow r;
 #pragma unroll
     for (int c = 0; c < 8; ++c) r.tb[c] = w[c];
@@ -653,6 +657,17 @@ __device__ __forceinline__ void walk_topk_body(const Views& v) {
     const InstU I = load_inst(v, b);
     if (I.status == 0) {
       const uint64_t local = u - (uint64_t)I.unit_begin + (uint64_t)I.local_off;
+      if constexpr (std::is_same_v<E, int32_t>) {
+        // int32 Q beyond the int32 walk's range: float64 tables, half screen
+        if (uniform_i32(gp((const Inst*)v.inst)[b].wide)) {
+          // the unit reads and writes the LDS rows as float64: keep the
+          // compiler from moving int64 accesses of other units across it
+          __asm__ volatile("" ::: "memory");
+          walk_unit_h16<kInt16RowStride>(v, b, I, local, lkey, lmask, pub, (double*)myc, lane);
+          __asm__ volatile("" ::: "memory");
+          continue;
+        }
+      }
       if constexpr (kHalf && std::is_same_v<E, float>) {
         walk_unit_h16(v, b, I, local, lkey, lmask, pub, myc, lane);
       } else if constexpr (kHalf) {

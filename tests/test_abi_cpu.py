@@ -102,7 +102,9 @@ def test_range_and_merge_argument_checks():
     L = _lib.lib()
     assert L.qubo_bf_range_workspace_size(40, 16, 0, 4) > 0
     assert L.qubo_bf_range_workspace_size(40, 16, 0, 0) == 0      # p_bits >= 1
-    assert L.qubo_bf_range_workspace_size(40, 16, 0, 21) == 0     # p_bits <= 20
+    assert L.qubo_bf_range_workspace_size(40, 16, 0, 28) > 0      # p_bits up to n - 12
+    assert L.qubo_bf_range_workspace_size(40, 16, 0, 29) == 0
+    assert L.qubo_bf_range_workspace_size(63, 8, 0, 51) > 0
     assert L.qubo_bf_range_workspace_size(14, 4, 1, 3) == 0       # p_bits <= n - 12
     ws = 1 << 40
     args = lambda pb, lo, hi: (FAKE, 30, 30, 0, 4, pb, lo, hi, FAKE, FAKE, FAKE, FAKE, ws, None)
@@ -153,3 +155,16 @@ def test_noalloc_rejects_before_any_hip_call(case):
                                  a["stream"])
     assert rc == -1
     assert L.qubo_last_error()
+
+
+def test_kprime_argument_checks():
+    L = _lib.lib()
+    assert L.qubo_bf_workspace_size_kp(20, 4, 0, 0) == L.qubo_bf_workspace_size(20, 4, 0)
+    assert L.qubo_bf_workspace_size_kp(30, 4, 64, 0) > L.qubo_bf_workspace_size(30, 4, 0)
+    assert L.qubo_bf_workspace_size_kp(20, 4, 3, 0) == 0    # kprime < k
+    assert L.qubo_bf_workspace_size_kp(20, 4, 65, 0) == 0   # kprime > 64
+    assert L.qubo_bf_workspace_size_kp(20, 4, 4, 1) > 0     # integer Q: kprime = k is the default
+    args = lambda kp: (FAKE, 10, 10, 0, 4, kp, FAKE, FAKE, FAKE, FAKE, 1 << 40, None)
+    assert L.qubo_bf_solve_kp(*args(2)) == -1
+    assert L.qubo_bf_solve_kp(*args(65)) == -1
+    assert b"kprime" in L.qubo_last_error()

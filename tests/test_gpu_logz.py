@@ -189,3 +189,17 @@ def test_nonfinite_beta_flags_only_that_instance(gpu_lib):
     assert np.isnan(lz[1]) and np.isnan(lz[2])
     for b in (0, 3):
         assert abs(lz[b] - oracle.logz(Q[b], float(betas[b]))) <= logz_tol(Q[b], float(betas[b]))
+
+
+def test_logz_rejects_a_nonzero_lower_triangle(gpu_lib):
+    from paper_2310_19373_amd import api
+
+    Q = inputs.random_f32(10, 870, scale=0.3)
+    full = Q + np.tril(np.full((10, 10), 0.25, dtype=np.float32), -1)
+    with pytest.raises(ValueError):
+        api.logz(torch.from_numpy(full).cuda(), 1.0)
+    # opted out: the lower triangle is ignored, as by the C ABI
+    lz = float(api.logz(torch.from_numpy(full).cuda(), 1.0, check_lower=False))
+    assert lz == float(api.logz(torch.from_numpy(Q).cuda(), 1.0))
+    assert abs(lz - oracle.logz(Q, 1.0)) <= logz_tol(Q, 1.0)
+

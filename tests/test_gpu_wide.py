@@ -5,7 +5,7 @@ float64 Q: the k best masks must equal the oracle's and the energies are the
 same canonical float64 sums (compared bit for bit); int64 Q: exact.  The
 float64 walk on float32-valued Q must reproduce the float32 path exactly (the
 same numbers, the same canonical rescoring).  int32 Q whose sum exceeds the
-int32 walk's 2^28 is solved through int64 by the Python layer."""
+int32 walk's 2^28 takes the same float64 tables inside the library, exactly."""
 import math
 
 import numpy as np
@@ -62,14 +62,87 @@ def test_i64_beyond_exact_range_is_reported(gpu_lib):
     assert ei.value.code == _lib.QUBO_ERR_RANGE
 
 
-def test_int32_with_large_sum_goes_through_int64(gpu_lib):
-    n = 24
-    Q = inputs.random_i32(n, 1200, -2**24, 2**24)
+def _raw_i32_solve(Q, k):
+    # straight through the C ABI with QUBO_I32: the library routes int32 Q
+    # beyond the int32 walk's 2^28 to its float64 tables itself
+    n = Q.shape[0]
+    L = _lib.lib()
+    Qd = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    wsb = L.qubo_bf_workspace_size(n, k, _lib.QUBO_I32)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    en = torch.empty(k, dtype=torch.int64, device="cuda")
+    mk = torch.empty(k, dtype=torch.int64, device="cuda")
+    st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    _lib.check(L.qubo_bf_solve(Qd.data_ptr(), n, n, _lib.QUBO_I32, k, en.data_ptr(), mk.data_ptr(), st.data_ptr(),
+                               ws.data_ptr(), wsb, None))
+    torch.cuda.synchronize()
+    return _np(en), _np(mk), int(st.item())
+
+
+@pytest.mark.parametrize("n,lo,hi,k", [(24, -2**24, 2**24, 10), (14, -2**31, 2**31 - 1, 64), (21, 0, 2**30, 3),
+                                       (27, -2**27, 2**27, 16), (26, -2**31, 2**31 - 1, 5)])
+def test_int32_with_large_sum_walks_exactly(gpu_lib, n, lo, hi, k):
+    Q = inputs.random_i32(n, 1200 + n, lo, hi)
     assert np.abs(Q.astype(np.int64)).sum() > 2**28
-    e, m = api.solve(Q, 10)
-    E, M = oracle.topk(Q, 10)
-    assert _u64(_np(m)) == _u64(M)
-    assert np.array_equal(_np(e), E)
+    print(f"i32 wide n={n} k={k}", flush=True)
+    e, m, st = _raw_i32_solve(Q, k)
+    E, M = oracle.topk(Q, k)
+    assert st == 0
+    assert _u64(m) == _u64(M)
+    assert np.array_equal(e, E)
+    e2, m2 = api.solve(Q, k)  # the Python layer passes int32 Q straight through
+    assert np.array_equal(_np(e2), e) and np.array_equal(_np(m2), m)
+
+
+def test_int32_wide_ties_and_extremes(gpu_lib):
+    # every entry at the int32 extremes: sums near 2^40, heavy ties
+    rng = np.random.default_rng(1250)
+    n = 22
+    Q = np.triu(rng.choice(np.array([-2**31, 0, 2**31 - 1], dtype=np.int64), (n, n))).astype(np.int32)
+    for k in (1, 4, 33):
+        e, m, st = _raw_i32_solve(Q, k)
+        E, M = oracle.topk(Q, k)
+        assert st == 0 and _u64(m) == _u64(M) and np.array_equal(e, E), k
+
+
+@pytest.mark.parametrize("half", [1, -1])
+def test_int32_batch_mixes_narrow_and_wide(gpu_lib, half):
+    # one batch: int16-screen, int32-screen and wide instances side by side,
+    # under both screen settings
+    rng = np.random.default_rng(1260)
+    ns = rng.integers(8, 25, 36).astype(np.int32)
+    nmax = int(ns.max())
+    Q = np.zeros((36, nmax, nmax), dtype=np.int32)
+    for b, n in enumerate(ns):
+        bound = [100, 30000, 2**26][b % 3]
+        Q[b, :n, :n] = np.triu(rng.integers(-bound, bound + 1, (n, n)))
+    old = _lib.get_tuning(_lib.TUNE_HALF_SCREEN)
+    _lib.set_tuning(_lib.TUNE_HALF_SCREEN, half)
+    try:
+        print(f"i32 mixed batch half={half}", flush=True)
+        e, m = api.solve_batched(Q, ns, 4)
+    finally:
+        _lib.set_tuning(_lib.TUNE_HALF_SCREEN, old)
+    e, m = _np(e), _np(m)
+    for b, n in enumerate(ns):
+        E, M = oracle.topk(Q[b, :n, :n], 4)
+        assert _u64(m[b]) == _u64(M), b
+        assert np.array_equal(e[b], E), b
+
+
+def test_int32_wide_ranges_merge_to_full(gpu_lib):
+    n, k, pb = 28, 6, 4
+    Q = inputs.random_i32(n, 1270, -2**29, 2**29)
+    parts = []
+    for lo, hi in ((0, 5), (5, 6), (6, 16)):
+        print(f"i32 wide range [{lo},{hi})", flush=True)
+        e, m = api.solve_range(Q, k, pb, lo, hi)
+        E, M = oracle.topk(Q, k, lo=lo << (n - pb), hi=hi << (n - pb))
+        assert _u64(_np(m)) == _u64(M) and np.array_equal(_np(e), E)
+        parts.append((e, m))
+    me, mm = api.merge_topk(parts, k)
+    fe, fm = api.solve(Q, k)
+    assert torch.equal(me, fe) and torch.equal(mm, fm)
 
 
 def test_f64_walk_reproduces_f32_path_on_float32_values(gpu_lib):
@@ -162,3 +235,53 @@ def test_f64_nonfinite_is_reported(gpu_lib):
     with pytest.raises(_lib.QuboError) as ei:
         api.solve(Q, 2)
     assert ei.value.code == _lib.QUBO_ERR_NONFINITE
+
+
+def _tied(n, seed, scale, dtype):
+    # entries in {-1, 0, 1} * scale: energies take few values, so many states tie
+    # at the k-th one and only the lower-mask rule decides between them
+    rng = np.random.default_rng(seed)
+    return np.triu(rng.integers(-1, 2, (n, n))).astype(dtype) * dtype(scale)
+
+
+@pytest.mark.parametrize("n", [19, 20, 21, 22, 23, 24])
+def test_i64_heavy_ties_single(gpu_lib, n):
+    # exact int64 path (K' = k, no certificate) with the threshold seed active
+    # (n >= 19): ties at the k-th energy must go to the lower natural mask
+    Q = _tied(n, 2000 + n, 2**30 + 7, np.int64)
+    for k in (1, 2, 3, 4):
+        print(f"i64 ties n={n} k={k}", flush=True)
+        e, m = api.solve(Q, k)
+        E, M = oracle.topk(Q, k)
+        assert _u64(_np(m)) == _u64(M), (n, k)
+        assert np.array_equal(_np(e), E), (n, k)
+
+
+@pytest.mark.parametrize("n", [15, 17, 20, 22])
+def test_integer_valued_f32_heavy_ties_single(gpu_lib, n):
+    # integer-valued float32 with sum |Q| <= 2^24: the exact float path (eps = 0)
+    Q = _tied(n, 2100 + n, 7, np.float32)
+    for k in (1, 5, 20):
+        print(f"f32 integer ties n={n} k={k}", flush=True)
+        e, m = api.solve(Q, k)
+        E, M = oracle.topk(Q, k)
+        assert _u64(_np(m)) == _u64(M), (n, k)
+        assert np.array_equal(_np(e), E), (n, k)
+
+
+@pytest.mark.parametrize("dtype,scale", [(np.int64, 2**30 + 7), (np.float32, 7), (np.float64, 3)])
+def test_heavy_ties_batched(gpu_lib, dtype, scale):
+    rng = np.random.default_rng(2200)
+    ns = rng.integers(15, 25, 24).astype(np.int32)
+    nmax = int(ns.max())
+    Q = np.zeros((24, nmax, nmax), dtype=dtype)
+    for b, n in enumerate(ns):
+        Q[b, :n, :n] = _tied(int(n), 2300 + b, scale, dtype)
+    for k in (1, 4):
+        print(f"batched ties {np.dtype(dtype).name} k={k}", flush=True)
+        e, m = api.solve_batched(Q, ns, k)
+        e, m = _np(e), _np(m)
+        for b, n in enumerate(ns):
+            E, M = oracle.topk(Q[b, :n, :n], k)
+            assert _u64(m[b]) == _u64(M), (b, k)
+            assert np.array_equal(e[b], E), (b, k)
