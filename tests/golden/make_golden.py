@@ -4,7 +4,7 @@ CPU oracle on the seeded workloads.
     python tests/golden/make_golden.py [name ...]
 
 Names: single_n20_f32, single_n32_i32, single_n40_f32_planted, logz_sample,
-batched_sample.  Each JSON file records the workload, the oracle call, the
+batched_sample, batched_mid, single_mid_f32, logz_general.  Each JSON file records the workload, the oracle call, the
 host thread count and the wall time.  Float energies are stored as Python
 float reprs (exact round trip of the float64 value).
 """
@@ -119,8 +119,68 @@ def batched_sample():
         "threads": oracle.max_threads(), "seconds": time.time() - t, "instances": rows})
 
 
+def batched_mid():
+    # argmin and runner-up of 72 instances of the 4096-instance workload, six
+    # for each n_b in 17..28 (the first six of that size in batch order)
+    Qp, ns = inputs.batched_4096()
+    picks = []
+    for n in range(17, 29):
+        picks += [int(b) for b in np.nonzero(ns == n)[0][:6]]
+    rows = []
+    t = time.time()
+    for b in sorted(picks):
+        n = int(ns[b])
+        E, M = oracle.topk(np.ascontiguousarray(Qp[b, :n, :n]), 2)
+        rows.append({"instance": b, "n": n, "energies": _energies(E), "masks": [int(m) for m in M]})
+    _dump("batched_mid", {
+        "workload": "4096 instances, n_b uniform [12,28], N(0,1) float32, seed 3 (six instances per n_b in 17..28)",
+        "call": "oracle.topk(Q_b, 2)", "threads": oracle.max_threads(), "seconds": time.time() - t,
+        "instances": rows})
+
+
+SINGLE_MID = [(27, 2700), (28, 2800), (29, 2900), (30, 3000), (31, 3100)]
+
+
+def single_mid_f32():
+    # single float32 solves at the sizes where the single-solve bit split
+    # changes (unit bits 9..11), N(0,1) entries
+    rows = []
+    t = time.time()
+    for n, seed in SINGLE_MID:
+        Q = inputs.random_f32(n, seed)
+        E, M = oracle.topk(Q, 16)
+        rows.append({"n": n, "seed": seed, "energies": _energies(E), "masks": [int(m) for m in M]})
+        print("  n", n, time.time() - t, flush=True)
+    _dump("single_mid_f32", {
+        "workload": "float32 N(0,1), inputs.random_f32(n, seed), k=16 (natural-order brute force)",
+        "call": "oracle.topk(Q, 16)", "threads": oracle.max_threads(), "seconds": time.time() - t,
+        "instances": rows})
+
+
+LOGZ_GENERAL = [(28, 2801, 0.5), (28, 2801, 4.0), (32, 3201, 0.5), (32, 3201, 4.0)]
+
+
+def logz_general():
+    # logZ, E_p[f] and the gradient of general Q (N(0, 1/n) float32 entries) at
+    # the largest sizes the log-partition calls take
+    rows = []
+    t = time.time()
+    for n, seed, beta in LOGZ_GENERAL:
+        Q = inputs.random_f32(n, seed, scale=1 / np.sqrt(n))
+        lz, mean = oracle.logz(Q, beta, with_mean=True)
+        G = oracle.grad(Q, beta, lz)
+        rows.append({"n": n, "seed": seed, "beta": beta, "logz": lz, "mean_energy": mean,
+                     "grad_upper": [float(v) for v in G[np.triu_indices(n)]]})
+        print("  n", n, "beta", beta, time.time() - t, flush=True)
+    _dump("logz_general", {
+        "workload": "float32 N(0,1/n), inputs.random_f32(n, seed, scale=1/sqrt(n)); logZ two-pass Neumaier, "
+                    "gradient Neumaier sum of p(x) x_i x_j",
+        "call": "oracle.logz(Q, beta, with_mean=True); oracle.grad(Q, beta, logz)",
+        "threads": oracle.max_threads(), "seconds": time.time() - t, "pairs": rows})
+
+
 ALL = {f.__name__: f for f in (single_n20_f32, single_n32_i32, single_n40_f32_planted, logz_sample,
-                               batched_sample)}
+                               batched_sample, batched_mid, single_mid_f32, logz_general)}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(ALL)):

@@ -125,3 +125,22 @@ def test_graph_replays_match_eager(gpu_lib):
     e, m = g.results()
     E, M = _oracle_all(Q2, ns2, 2)
     assert np.array_equal(m.cpu().numpy().astype(np.uint64), M) and np.array_equal(e.cpu().numpy(), E)
+
+
+def test_batched_config4_mid_sizes_against_golden(gpu_lib):
+    # the same 4096-instance batch with k=2: six instances of every n_b in
+    # 17..28 against their stored oracle top-2 (argmin and runner-up)
+    from paper_2310_19373_amd import api
+
+    Q, ns = inputs.batched_4096()
+    print("batched config: 4096 instances, k=2", flush=True)
+    e, m = api.solve_batched(Q, ns, 2)
+    e, m = e.cpu().numpy(), m.cpu().numpy().astype(np.uint64)
+    g = json.load(open(os.path.join(GOLDEN, "batched_mid.json")))
+    assert len(g["instances"]) >= 64
+    assert sorted({row["n"] for row in g["instances"]}) == list(range(17, 29))
+    for row in g["instances"]:
+        b = row["instance"]
+        assert int(ns[b]) == row["n"], b
+        assert [int(x) for x in m[b]] == row["masks"], b
+        assert e[b].tolist() == row["energies"], b
