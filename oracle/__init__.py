@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqubo_oracle.so")
+# QUBO_ORACLE_LIB: another build of the same library (the sanitizer run of the CPU tests)
+LIB_PATH = os.environ.get("QUBO_ORACLE_LIB") or os.path.join(_HERE, "libqubo_oracle.so")
 
 _lib = None
 

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqubo_gray_cpu.so")
+# QUBO_GRAY_LIB: another build of the same library (the sanitizer run of the CPU tests)
+LIB_PATH = os.environ.get("QUBO_GRAY_LIB") or os.path.join(_HERE, "libqubo_gray_cpu.so")
 
 _lib = None
 
