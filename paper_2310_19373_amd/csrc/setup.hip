@@ -113,9 +113,21 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
   }
   if (tid == nt - 1) {
     const uint64_t tu = (uint64_t)su[nt - 1];
+    // about four pulls per wave or more, so the queue balances the tail
+    int64_t c = su[nt - 1] / ((int64_t)(pp.waves > 0 ? pp.waves : 1) * 4);
+    if (c > pp.chunk_cap) c = pp.chunk_cap;
+    if (c < 1) c = 1;
+    v.hdr->chunk = (int32_t)c;
+    // Each segment's counter starts past the static first runs of its waves
+    // (one run of c units per wave of the workgroups x, x + 8, ...; see
+    // WorkIter): the walk takes those without an atomic.
+    const int64_t blocks = pp.waves / kWavesPerBlock;
     for (int x = 0; x < kXcds; ++x) {
-      v.hdr->seg[x].next = tu * (uint64_t)x / kXcds;
-      v.hdr->seg[x].end = tu * (uint64_t)(x + 1) / kXcds;
+      const uint64_t b0 = tu * (uint64_t)x / kXcds, b1 = tu * (uint64_t)(x + 1) / kXcds;
+      const uint64_t wx = blocks > x ? (uint64_t)((blocks - x + kXcds - 1) / kXcds) * kWavesPerBlock : 0;
+      const uint64_t first = b0 + wx * (uint64_t)c;
+      v.hdr->seg[x].next = v.dyn ? (first < b1 ? first : b1) : b0;
+      v.hdr->seg[x].end = b1;
     }
     v.hdr->total_units = tu;
     v.hdr->direct_count = 0;
@@ -124,10 +136,6 @@ __global__ void __launch_bounds__(1024) plan_kernel(Views v, const int32_t* ns, 
     v.hdr->batch = batch;
     v.hdr->nmax = v.nmax;
     v.hdr->waves = pp.waves;
-    // about four pulls per wave or more, so the queue balances the tail
-    int64_t c = su[nt - 1] / ((int64_t)(pp.waves > 0 ? pp.waves : 1) * 4);
-    if (c > pp.chunk_cap) c = pp.chunk_cap;
-    v.hdr->chunk = c < 1 ? 1 : (int32_t)c;
   }
 }
 

@@ -110,36 +110,97 @@ __device__ __forceinline__ uint64_t take_units(const Views& v, int sg, int lane,
 }
 
 // Work distribution of the persistent walks, in runs of consecutive units.
-// Dynamic (v.dyn): a wave starts on the queue segment of its XCD (workgroup
-// index mod kXcds) and, once that is empty, moves on to the following
-// segments only, so its units increase monotonically.  Within a segment,
-// guided self-scheduling: a pull takes min(cap, rest / (2 x waves per
-// segment)) units (at least 1), rest being what the segment had left after
-// the wave's previous pull, so runs shrink towards the end.  Static: wave w
-// of G takes runs w, w+G, ... of cap units.  Either way a wave meets each
-// instance in one contiguous stretch, and its candidate list carries over
-// between the units of a run.
+// Dynamic (v.dyn): the unit range is cut into kXcds segments, and a wave works
+// on the segment of its XCD (workgroup index mod kXcds) first.
+//   * Its first run is assigned statically: the planner started each
+//     segment's counter past one run of `cap` units per wave of that segment
+//     (the waves of workgroups x, x + 8, ... in order), so the grid starts
+//     without a burst of atomics on eight counters.
+//   * Later runs are pulled with an atomic add (guided self-scheduling: a pull
+//     takes min(cap, rest / (2 x waves per segment)) units, at least 1, rest
+//     being what the segment had left after the wave's previous pull, so runs
+//     shrink towards the end).
+//   * Near a segment's end, and after a pull that found it empty, the wave
+//     first reads the eight counters with one lane-parallel load and pulls
+//     from the first later segment that still has units, or stops: a drained
+//     segment is not hit by one atomic from every wave of the grid.
+// A wave only moves on to later segments, so its units increase
+// monotonically.  Static (!v.dyn): wave w of G takes runs w, w+G, ... of cap
+// units.  Either way a wave meets each instance in one contiguous stretch,
+// and its candidate list carries over between the units of a run.
+//
+// The static first runs assume the grid the planner was told (Header.waves
+// waves, in blocks of kWavesPerBlock): every launch of a walk uses that grid.
 struct WorkIter {
-  uint64_t total, cap, want, waves2, u = 0, u_end = 0, next_static, seg_end;
+  uint64_t total, cap, want, waves2, u = 0, u_end = 0, next_static, seg_end, left;
   int64_t stride;
   int sg;
-  bool dyn;
+  bool dyn, first;
   __device__ WorkIter(const Views& v, uint64_t total_units) {
+    const gptr<const Header> h = gp((const Header*)v.hdr);
     total = total_units;
-    cap = (uint64_t)(uint32_t)uniform_i32(gp((const Header*)v.hdr)->chunk);
+    cap = (uint64_t)(uint32_t)uniform_i32(h->chunk);
     want = cap;
     dyn = v.dyn != 0;
+    first = true;
     next_static = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     stride = (int64_t)gridDim.x * kWavesPerBlock;
     const uint64_t per_seg = (uint64_t)stride / kXcds;
     waves2 = 2 * (per_seg > 0 ? per_seg : 1);
     sg = (int)(blockIdx.x % kXcds);
-    seg_end = uniform_u64(gp((const Header*)v.hdr)->seg[sg].end);
+    seg_end = uniform_u64(h->seg[sg].end);
+    left = ~0ull;
+  }
+  // The first run of this wave: units [begin + rank * cap, + cap) of its
+  // segment, clipped to the segment (empty for a wave beyond the planned
+  // grid or a segment with fewer units than waves).
+  __device__ __forceinline__ bool static_run(const Views& v) {
+    const uint64_t pw = (uint64_t)(uint32_t)uniform_i32(gp((const Header*)v.hdr)->waves);
+    const uint64_t blocks = pw / kWavesPerBlock;
+    const uint64_t bi = blockIdx.x;
+    if (bi >= blocks) return false;
+    const uint64_t x = (uint64_t)sg;
+    const uint64_t rank = (bi / kXcds) * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint64_t b0 = total * x / kXcds;
+    // units the segment keeps for pulls after the static runs (as the planner)
+    const uint64_t wx = blocks > x ? (blocks - x + kXcds - 1) / kXcds * kWavesPerBlock : 0;
+    const uint64_t sdone = b0 + wx * cap < seg_end ? b0 + wx * cap : seg_end;
+    left = seg_end - sdone;
+    const uint64_t c = b0 + rank * cap;
+    if (c >= seg_end) return false;
+    u = c;
+    u_end = c + cap < seg_end ? c + cap : seg_end;
+    return true;
   }
   __device__ __forceinline__ bool next(const Views& v, int lane, uint64_t& unit) {
     if (u >= u_end) {
       if (dyn) {
-        for (;;) {  // at most kXcds segments; every value here is wave-uniform
+        if (first) {
+          first = false;
+          if (static_run(v)) {
+            unit = u++;
+            return true;
+          }
+        }
+        for (;;) {  // every value here is wave-uniform
+          if (uniform_u64(left) <= uniform_u64(waves2) * cap) {
+            // near or past the end of the segment: look at all counters
+            const gptr<QueueSeg> seg = gp(v.hdr->seg);
+            uint64_t nx = ~0ull, ex = 0;
+            if (lane < kXcds) {
+              nx = __hip_atomic_load(&seg[lane].next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ex = seg[lane].end;
+            }
+            const uint64_t avail = ballot(lane < kXcds && lane >= uniform_i32(sg) && nx < ex);
+            if (!avail) return false;
+            const int s = __builtin_ctzll(avail);
+            if (s != uniform_i32(sg)) {
+              sg = s;
+              seg_end = readlane_u64(ex, s);
+              want = cap;
+            }
+            left = ~0ull;
+          }
           const int s = uniform_i32(sg);
           const uint64_t w = uniform_u64(want);
           const uint64_t e = uniform_u64(seg_end);
@@ -147,14 +208,12 @@ struct WorkIter {
           if (c < e) {
             u = c;
             u_end = c + w < e ? c + w : e;
-            const uint64_t share = (e - u_end) / waves2;
+            left = e - u_end;
+            const uint64_t share = left / waves2;
             want = share < 1 ? 1 : (share > cap ? cap : share);
             break;
           }
-          sg = s + 1;
-          if (sg >= kXcds) return false;
-          seg_end = uniform_u64(gp((const Header*)v.hdr)->seg[sg].end);
-          want = cap;
+          left = 0;  // drained: the next round looks before it pulls
         }
       } else {
         const uint64_t c = next_static;
@@ -224,6 +283,16 @@ __device__ __forceinline__ typename Ar<E>::W lane_init_with(const Views& v, int 
   const int64_t nm = v.nmax;
   const gptr<const W> qs = gp((const W*)v.qs) + (int64_t)b * nm * nm;
   const gptr<const W> ei = gp((const W*)v.ei) + (int64_t)b * 64;
+  // The lane record's energy and inner cross fields and (kLaneEI) this
+  // lane's E_I entry are read first, unconditionally (the record's unused
+  // fields are zero), so that their latency overlaps the tile rows' instead
+  // of following it one load at a time: [0] lane-bit energy, [1 + u] inner
+  // cross field u.
+  const gptr<const W> lt = gp((const W*)v.lt) + ((int64_t)b * 64 + lane) * kLaneRec;
+  W lrec[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) lrec[i] = lt[i];
+  const W eil = (kLaneEI && lane < NB) ? ei[lane] : (W)0;
   // tile sums: S (lane t < tp0) = sum_{set tile bits k} S(t, tp0+k);
   // R (tile row t = lane, bit t set) = sum_{set tile bits k >= t} Q(tp0+t, tp0+k)
   W S = 0, R = 0;
@@ -253,21 +322,26 @@ __device__ __forceinline__ typename Ar<E>::W lane_init_with(const Views& v, int 
   else etile = (W)uniform_u64((uint64_t)etile);
   myc[kTileRow * kWave + lane] = S;
   // lane record + tile sums
-  const gptr<const W> lt = gp((const W*)v.lt) + ((int64_t)b * 64 + lane) * kLaneRec;
-  W EP = etile + lt[0];
+  W EP = etile + lrec[0];
   for (int a = 0; a < I.L; ++a)
     if ((lane >> a) & 1) EP += myc[kTileRow * kWave + pos0 + a];
   W cI[6];
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
-    cI[u] = u < I.B ? lt[1 + u] + myc[kTileRow * kWave + u] : (W)0;
+    cI[u] = u < I.B ? lrec[1 + u] + myc[kTileRow * kWave + u] : (W)0;
     myc[(kCIRow + u) * kWave + lane] = cI[u];
   }
-  for (int l = 0; l < I.no; ++l) myc[l * kWave + lane] = lt[8 + l] + myc[kTileRow * kWave + I.B + l];
-  // kLaneEI: lane j loads E_I(j) (one coalesced load) and the loop reads it
-  // back by lane, for kernels at 128 VGPRs where 64 entries loaded per lane
-  // (128 VGPRs in flight) would spill
-  const W eil = (kLaneEI && lane < NB) ? ei[lane] : (W)0;
+  {  // outer cross fields: all loads in flight together, then the stores
+    W lo[kMaxOuter];
+#pragma unroll
+    for (int l = 0; l < kMaxOuter; ++l) lo[l] = lt[8 + l];
+#pragma unroll
+    for (int l = 0; l < kMaxOuter; ++l)
+      if (l < I.no) myc[l * kWave + lane] = lo[l] + myc[kTileRow * kWave + I.B + l];
+  }
+  // kLaneEI: lane j loaded E_I(j) above (one coalesced load) and the loop
+  // reads it back by lane, for kernels at 128 VGPRs where 64 entries loaded
+  // per lane (128 VGPRs in flight) would spill
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     W cj;

@@ -119,6 +119,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
 
+  const double g0 = load_gthr(v, b);  // issued first: its latency overlaps the set-up's
   // ---- lane init: prefix energy, inner table, outer cross fields
   E C[NB];
   const W EP = lane_init<E, NB>(v, b, I, local, valid, myc, lane, C);
@@ -130,7 +131,6 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   using Acc = std::conditional_t<kInt, int32_t, double>;
   // pub also tracks the lowest threshold seen, so a wave publishes (one
   // atomic) only a value below what the instance already has
-  const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
   double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
   Acc Dp = kInt ? (Acc)((int32_t)thr - (int32_t)EP) : (Acc)(thr - (double)EP);
@@ -330,12 +330,12 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
   frexp(hs, &hexp);
   hexp -= 1;  // hs = 2^hexp
   h2 C16[2][16];
+  const double g0 = load_gthr(v, b);  // issued first: its latency overlaps the set-up's
   const double EP = lane_init_with<float, 64, true>(v, b, I, local, valid, myc, lane, [&](int j, bool ok, double cj) {
     const float f = ok ? (float)cj : __builtin_inff();
     C16[(j >> 4) & 1][j & 15][j >> 5] = (_Float16)__builtin_ldexpf(f, hexp);
   });
 
-  const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
   double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
   double Dp = (thr - EP) * hs;  // the float32 walk's Dp, scaled
@@ -505,12 +505,12 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
   // C'(j), j = c | a << 4, as int16 pairs (a, a + 2); invalid entries 32767
+  const double g0 = load_gthr(v, b);  // issued first: its latency overlaps the set-up's
   s2 C16[2][16];
-  const int64_t EP = lane_init_with<int32_t, 64>(v, b, I, local, valid, myc, lane, [&](int j, bool ok, int64_t cj) {
+  const int64_t EP = lane_init_with<int32_t, 64, true>(v, b, I, local, valid, myc, lane, [&](int j, bool ok, int64_t cj) {
     C16[(j >> 4) & 1][j & 15][j >> 5] = (short)(ok ? cj : kInt16Limit);
   });
 
-  const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
   double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
   int32_t Dp = (int32_t)thr - (int32_t)EP;  // the int32 walk's Dp

@@ -203,3 +203,23 @@ def test_logz_rejects_a_nonzero_lower_triangle(gpu_lib):
     assert lz == float(api.logz(torch.from_numpy(Q).cuda(), 1.0))
     assert abs(lz - oracle.logz(Q, 1.0)) <= logz_tol(Q, 1.0)
 
+
+
+def test_logz_general_q_at_28_and_32_against_golden(gpu_lib):
+    # general Q (N(0, 1/n)) at the largest log-partition sizes, where each
+    # lane's float32 sums inside a work unit are longest: stored float64 oracle
+    # logZ, E_p[f] and gradient
+    g = json.load(open(os.path.join(GOLDEN, "logz_general.json")))
+    assert sorted({row["n"] for row in g["pairs"]}) == [28, 32]
+    for row in g["pairs"]:
+        n, beta = row["n"], row["beta"]
+        Q = inputs.random_f32(n, row["seed"], scale=1 / math.sqrt(n))
+        lz, G, gb = _gpu_logz_grad(Q, beta)
+        Gref = np.zeros((n, n))
+        Gref[np.triu_indices(n)] = row["grad_upper"]
+        err = _rel(G, Gref)
+        print(f"  n={n} beta={beta}: |dlogZ| {abs(lz - row['logz']):.3e}, grad max-norm rel {err:.3e}, "
+              f"dlogZ/dbeta rel {abs(gb + row['mean_energy']) / max(1.0, abs(row['mean_energy'])):.3e}", flush=True)
+        assert abs(lz - row["logz"]) <= logz_tol(Q, beta), (n, beta)
+        assert err <= 1e-4, (n, beta, err)
+        assert abs(gb + row["mean_energy"]) <= 1e-4 * max(1.0, abs(row["mean_energy"])), (n, beta)
