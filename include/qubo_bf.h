@@ -285,7 +285,8 @@ const char* qubo_version(void);
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
  *                                 (0, the default, reads back as 0 and means
  *                                 16 for the half-screen walk of float32,
- *                                 float64 and int64 Q, 12 otherwise)
+ *                                 float64 and int64 Q, 12 otherwise); never
+ *                                 more than the walk kernel keeps resident
  *   QUBO_TUNE_KPRIME              candidate list length override (float path;
  *                                 values below k make the certificate fail)
  *   QUBO_TUNE_CHUNK_SINGLE        work units per queue pull, single solve

@@ -102,10 +102,12 @@ int device_cus() {
   return cache[dev];
 }
 
-// Waves of a persistent grid: the knob, else `auto_per_cu` per CU (the
-// resident count of the kernel launched).
-int grid_waves(int auto_per_cu = 12) {
-  const int per_cu = tuning().waves_per_cu > 0 ? tuning().waves_per_cu : auto_per_cu;
+// Waves of a persistent grid: the knob, else `auto_per_cu` per CU, never
+// more than the kernel keeps resident (`blocks_per_cu` workgroups of
+// kWavesPerBlock waves per CU).
+int grid_waves(int auto_per_cu, int blocks_per_cu) {
+  int per_cu = tuning().waves_per_cu > 0 ? tuning().waves_per_cu : auto_per_cu;
+  if (per_cu > blocks_per_cu * kWavesPerBlock) per_cu = blocks_per_cu * kWavesPerBlock;
   long w = (long)device_cus() * clampi(per_cu, 1, 32);
   if (w > kMaxGridWaves) w = kMaxGridWaves;
   return (int)(w - w % kWavesPerBlock);
@@ -347,7 +349,7 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
   const bool half = tuning().half_screen > 0 && pp.inner == kInner;
   v.h16 = half ? 1 : 0;
   // the half-screen walk (float32, float64 and int64 Q) runs 4 waves per SIMD
-  int waves = grid_waves(v.h16 && dt != kDtI32 ? 16 : 12);
+  int waves = grid_waves(v.h16 && dt != kDtI32 ? 16 : 12, walk_topk_blocks_per_cu(dt, v.h16));
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;
     waves += (kWavesPerBlock - waves % kWavesPerBlock) % kWavesPerBlock;
@@ -650,7 +652,7 @@ int qubo_logz_fwd(int batch, const float* Q, int nmax, const int32_t* ns, const 
   const Layout L = make_layout(batch, nmax, pp, 1, 0, true);
   const Views v = make_views(ws, L, batch, nmax);
   hipStream_t s = (hipStream_t)hip_stream;
-  const int waves = grid_waves();
+  const int waves = grid_waves(12, walk_exp_blocks_per_cu());
   pp.waves = waves;
   const SplitH sh = split_host(nmax, pp);
   const int64_t steps_bound = (int64_t)batch << sh.no;
@@ -680,7 +682,7 @@ static int run_moment_walk(int batch, const float* Q, int nmax, const int32_t* n
   const Layout L = make_layout(batch, nmax, pp, np, 0, true);
   const Views v = make_views(ws, L, batch, nmax);
   hipStream_t s = (hipStream_t)hip_stream;
-  const int waves = grid_waves();
+  const int waves = grid_waves(12, walk_grad_blocks_per_cu());
   pp.waves = waves;
   const SplitH sh = split_host(nmax, pp);
   const int64_t steps_bound = (int64_t)batch << sh.no;
@@ -737,7 +739,7 @@ int qubo_logz_sample(int batch, const float* Q, int nmax, const int32_t* ns, con
   v.lanepart = v.part + units_bound;
   double* cum = v.part + units_bound * (kSamplePart - 1);
   hipStream_t s = (hipStream_t)hip_stream;
-  const int waves = grid_waves();
+  const int waves = grid_waves(12, walk_exp_blocks_per_cu());
   pp.waves = waves;
   const int64_t steps_bound = (int64_t)batch << sh.no;
   HIPCHK(launch_plan(v, ns, 0, beta, pp, s));

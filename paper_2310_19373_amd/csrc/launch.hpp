@@ -68,6 +68,14 @@ hipError_t launch_prep_inst(const Views& v, const void* q, int64_t ldq, int64_t 
 hipError_t launch_prep_walk(const Views& v, int dt, int inner, int64_t steps_bound, bool seed, hipStream_t s);
 // persistent top-k walk.
 hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s);
+// Workgroups of a persistent walk that one compute unit holds at once (the
+// occupancy of the kernel launch_walk_topk / launch_walk_exp /
+// launch_walk_grad picks).  A persistent grid never exceeds it: a workgroup
+// that is not resident from the start would only begin once others have
+// finished, and a wave's first run of units is assigned to it statically.
+int walk_topk_blocks_per_cu(int dt, int h16);
+int walk_exp_blocks_per_cu();
+int walk_grad_blocks_per_cu();
 // merge candidate lists, rescore in float64 / int64, certificate, outputs.
 hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int64_t inst_stride, int dt,
                                 int k, void* energies, uint64_t* masks, int32_t* status, int waves_per_inst,

@@ -1042,6 +1042,26 @@ hipError_t launch_prep_exp_tables(const Views& v, const float* beta, int inner, 
   return hipGetLastError();
 }
 
+namespace {
+int occupancy_blocks(const void* kernel) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+}  // namespace
+
+int walk_exp_blocks_per_cu() {
+  static int cache = 0;
+  if (!cache) cache = occupancy_blocks((const void*)walk_exp_fac_kernel);
+  return cache;
+}
+
+int walk_grad_blocks_per_cu() {
+  static int cache = 0;
+  if (!cache) cache = occupancy_blocks((const void*)walk_grad_fac_kernel);
+  return cache;
+}
+
 hipError_t launch_walk_exp(const Views& v, const float* beta, int waves, hipStream_t s) {
   const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
   hipLaunchKernelGGL(walk_exp_fac_kernel, dim3(blocks), dim3(kBlock), 0, s, v, beta);

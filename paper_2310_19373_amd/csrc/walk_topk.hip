@@ -706,6 +706,29 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 
 }  // namespace
 
+namespace {
+int occupancy_blocks(const void* kernel) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+}  // namespace
+
+int walk_topk_blocks_per_cu(int dt, int h16) {
+  // one query per kernel, cached (the answer is fixed for the code object)
+  static int cache[5] = {0, 0, 0, 0, 0};
+  const int i = (dt == kDtI32 && h16) ? 0 : dt == kDtI32 ? 1 : h16 ? 2 : dt_wide(dt) ? 3 : 4;
+  if (!cache[i]) {
+    const void* k = i == 0   ? (const void*)walk_topk_i16_kernel
+                    : i == 1 ? (const void*)walk_topk_kernel<int32_t>
+                    : i == 2 ? (const void*)walk_topk_h16_kernel
+                    : i == 3 ? (const void*)walk_topk_f64_kernel
+                             : (const void*)walk_topk_kernel<float>;
+    cache[i] = occupancy_blocks(k);
+  }
+  return cache[i];
+}
+
 hipError_t launch_walk_topk(const Views& v, int dt, int waves, hipStream_t s) {
   const int blocks = max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
   if (dt == kDtI32 && v.h16)
