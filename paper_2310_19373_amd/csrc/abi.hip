@@ -42,7 +42,7 @@ constexpr int kMaxGridWaves = 8192;  // sizing bound of the persistent grid
 struct Tuning {
   int single_outer = 12;
   int single_unit = 14;
-  int batched_outer = 8;
+  int batched_outer = 9;
   int waves_per_cu = 0;  // 0: 16 for the half-screen walk, 12 for the others
   int kprime = 0;
   int chunk_single = 2;

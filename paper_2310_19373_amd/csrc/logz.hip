@@ -226,6 +226,7 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
     const int qoff = (lane & 15) * 16;
     double K = EP;  // E_P + X_PO(p, g(t)): the lane's share of the step's constant
     double r = 0.0, S = 0.0;
+    double lbias = 0.0;  // the lane's sum is S * 2^-lbias
     if constexpr (PASS == 0) {
       float cmin = 0.f;
       if (!(v.factor && factor_ok(C, bbf, valid, cmin))) {
@@ -236,27 +237,30 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
       const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(gp((const float*)v.etab) + I.tab_off * kInnerStates), (short)0,
           (int)(steps * (uint32_t)(kInnerStates * sizeof(float))), 0x00020000);
-      const gptr<const double> tref = gp(v.tref) + I.tab_off;
+      // Exponents in units of bb: step t's block factor is 2^(ntau(t) + P),
+      // ntau(t) = -bb (min_j T' + E_O)(t) from the table, P = -bb (cm + K) +
+      // R the lane's part, R = bb r the lane's reference; a flip of outer bit
+      // l moves K by +-c_l, so P by -+bb c_l (the first three bits' products
+      // held in registers).  Block sums are accumulated in float32 over a
+      // group of eight steps (each at most 64 * 2^kRebase) and then in float64.
+      const gptr<const double> ntau = gp(v.tref) + I.tab_off;
       const double cm = (double)cmin;
-      r = cm + tref[0] + K;
-      f32x4 bn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, qoff, 0, 0));
-      double trn = tref[0];
-      for (uint32_t t = 0; t < steps; ++t) {
-        const f32x4 bc = bn;
-        const double trc = trn;
-        const uint32_t tt = t + 1 < steps ? t + 1 : t;
-        bn = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, qoff, (int)(tt * 256u), 0));
-        trn = tref[tt];
-        if (t) {
-          const int l = __builtin_ctz(t);
-          K = __builtin_fma(((t >> (l + 1)) & 1) ? -1.0 : 1.0, myc[l * kWave + lane], K);
-        }
-        const double lt = cm + trc + K;  // lower bound of the block's values
-        double ct = -bb * (lt - r);
+      const double nt0 = ntau[0];
+      double R = bb * (cm + EP) - nt0;  // so that the first block's exponent is 0
+      double P = -nt0;
+      const double bc0 = I.no > 0 ? bb * myc[lane] : 0.0;
+      const double bc1 = I.no > 1 ? bb * myc[kWave + lane] : 0.0;
+      const double bc2 = I.no > 2 ? bb * myc[2 * kWave + lane] : 0.0;
+      float Sf = 0.f;
+      auto body = [&](const f32x4& bc, double nt) {
+        double ct = nt + P;
         if (__builtin_expect(ballot(ct > kRebase) != 0, 0)) {  // rare: move the lane's reference
           if (ct > kRebase) {
-            S *= (double)exp2_fast((float)-ct);
-            r = lt;
+            // S 2^-R is kept: the reference rises to the block's bound
+            S = (S + (double)Sf) * (double)exp2_fast((float)-ct);
+            Sf = 0.f;
+            R -= ct;
+            P -= ct;
             ct = 0.0;
           }
         }
@@ -265,8 +269,55 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
         block_dot<1>(acc, bc.y, C);
         block_dot<2>(acc, bc.z, C);
         block_dot<3>(acc, bc.w, C);
-        S = __builtin_fma((double)((acc[0] + acc[1]) + (acc[2] + acc[3])), (double)exp2_fast((float)ct), S);
+        Sf = __builtin_fmaf((acc[0] + acc[1]) + (acc[2] + acc[3]), exp2_fast((float)ct), Sf);
+      };
+      auto load = [&](uint32_t t, f32x4& bv, double& nt) {
+        const uint32_t tt = t < steps ? t : steps - 1;
+        bv = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, qoff, (int)(tt * 256u), 0));
+        nt = ntau[tt];
+      };
+      f32x4 bn;
+      double nn;
+      load(0, bn, nn);
+      if (steps < 8) {
+        for (uint32_t t = 0; t < steps; ++t) {
+          const f32x4 bcur = bn;
+          const double ncur = nn;
+          load(t + 1, bn, nn);
+          if (t) {
+            const int l = __builtin_ctz(t);
+            P = __builtin_fma(((t >> (l + 1)) & 1) ? bb : -bb, myc[l * kWave + lane], P);
+          }
+          body(bcur, ncur);
+        }
+      } else {
+        // groups of eight steps t = 8q + r: bit 0 turns on at r = 1, 5 and off
+        // at 3, 7; bit 1 on at 2, off at 6; bit 2 at 4 (off for odd q); bit
+        // 3 + CTZ(q) at r = 0 (q > 0)
+        const uint32_t groups = steps >> 3;
+        for (uint32_t q = 0; q < groups; ++q) {
+          if (q) {
+            const int l = 3 + __builtin_ctz(q);
+            P = __builtin_fma(((q >> (l - 2)) & 1) ? bb : -bb, myc[l * kWave + lane], P);
+          }
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            const f32x4 bcur = bn;
+            const double ncur = nn;
+            load(8 * q + rr + 1, bn, nn);
+            if (rr == 1 || rr == 5) P -= bc0;
+            else if (rr == 3 || rr == 7) P += bc0;
+            else if (rr == 2) P -= bc1;
+            else if (rr == 6) P += bc1;
+            else if (rr == 4) P += (q & 1) ? bc2 : -bc2;
+            body(bcur, ncur);
+          }
+          S += (double)Sf;
+          Sf = 0.f;
+        }
       }
+      S += (double)Sf;
+      lbias = R;
     } else {
       // direct form.  beta = 0: a tiny negative slope keeps the sentinel entries (+inf) at
       // weight 0 without changing any valid weight.
@@ -309,7 +360,8 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
       }
     }
     // log2 of the lane's sum: log2 S - bb r
-    const double l = (valid && S > 0.0) ? log2(S) - bb * r : -__builtin_inf();
+    if constexpr (PASS == 1) lbias = bb * r;
+    const double l = (valid && S > 0.0) ? log2(S) - lbias : -__builtin_inf();
     const double lu = wave_lse2(l);
     if (lane == 0) gp(v.part)[u] = lu;
     if (v.lanepart) gp(v.lanepart)[u * kWave + lane] = l;
@@ -355,7 +407,8 @@ __global__ void __launch_bounds__(256) prep_exp_tables_kernel(Views v, const flo
   const int64_t steps = int64_t(1) << I->no;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int width = 1 << inner;
-  const float bbf = (float)(fabs((double)beta[b]) * kLog2e);
+  const double bb = fabs((double)beta[b]) * kLog2e;
+  const float bbf = (float)bb;
   const float* tab = (const float*)v.tab + I->tab_off * width;
   float* etab = (float*)v.etab + I->tab_off * width;
   const int64_t c0 = (int64_t)blockIdx.y * 64;
@@ -365,7 +418,7 @@ __global__ void __launch_bounds__(256) prep_exp_tables_kernel(Views v, const flo
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
     if (lane < width) etab[t * width + lane] = exp2_fast(-bbf * (tv - m));
-    if (lane == 0) v.tref[I->tab_off + t] = (double)m + v.eod[I->tab_off + t];
+    if (lane == 0) v.tref[I->tab_off + t] = -bb * ((double)m + v.eod[I->tab_off + t]);
   }
 }
 
@@ -529,17 +582,22 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
 #pragma unroll
     for (int i = 0; i < kGradMaxOuter * (kGradMaxOuter - 1) / 2; ++i) Bo[i] = 0.f;
 
-    double K = EP;  // E_P + X_PO(p, g(t)), moved along the walk
-    // Block sums of one step: y[0] = s = sum_j w(t, j), y[1 + a] = v_a =
-    // sum_j w(t, j) j_a; W[j] += w(t, j).  The caller has moved K to step t.
+    // Direct form: K = E_P + X_PO(p, g(t)), moved along the walk.  Factored
+    // form: the exponent -bb (cm + K) - logZ log2(e) of the step factor g,
+    // moved the same way (a flip of outer bit l moves K by +-c_l); the table
+    // holds the step's -bb (min_j T' + E_O).
     const double cm = (double)cmin;
+    double K = EP;
+    double Pg = -bb * (cm + EP) - lz2;
+    // Block sums of one step: y[0] = s = sum_j w(t, j), y[1 + a] = v_a =
+    // sum_j w(t, j) j_a; W[j] += w(t, j).  The caller has moved K / Pg to step t.
     const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_body
     auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1]) {
       float w[kGradStates];
       float va[kGradInner];
       if constexpr (decltype(fc)::value) {
-        // sc = tref(t); weight = g * a_j * b(t, j) <= 1, g <= 2^kSafeExp2
-        const float g = exp2_fast((float)(-bb * (cm + sc + K) - lz2));
+        // sc = -bb (min_j T' + E_O)(t); weight = g * a_j * b(t, j) <= 1, g <= 2^kSafeExp2
+        const float g = exp2_fast((float)(sc + Pg));
         block_prod8<0, 0>(w, tc.x, C);
         block_prod8<0, 1>(w, tc.x, C);
         block_prod8<1, 0>(w, tc.y, C);
@@ -571,7 +629,10 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
       tv = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(trs, qoff, (int)(tt * 128u), 0));
       sv = scal[tt];
     };
-    auto kflip = [&](int l, bool off) { K = __builtin_fma(off ? -1.0 : 1.0, myc[l * kWave + lane], K); };
+    auto kflip = [&](int l, bool off) {
+      if constexpr (fac) Pg = __builtin_fma(off ? bb : -bb, myc[l * kWave + lane], Pg);
+      else K = __builtin_fma(off ? -1.0 : 1.0, myc[l * kWave + lane], K);
+    };
 
     auto walk = [&](auto fc) {
       if (steps < 8) {
