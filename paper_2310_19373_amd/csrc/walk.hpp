@@ -283,15 +283,19 @@ __device__ __forceinline__ typename Ar<E>::W lane_init_with(const Views& v, int 
   const int64_t nm = v.nmax;
   const gptr<const W> qs = gp((const W*)v.qs) + (int64_t)b * nm * nm;
   const gptr<const W> ei = gp((const W*)v.ei) + (int64_t)b * 64;
-  // The lane record's energy and inner cross fields and (kLaneEI) this
-  // lane's E_I entry are read first, unconditionally (the record's unused
-  // fields are zero), so that their latency overlaps the tile rows' instead
-  // of following it one load at a time: [0] lane-bit energy, [1 + u] inner
-  // cross field u.
+  // kLaneEI (the half-width screens, whose set-up has registers to spare
+  // before C' exists): the lane record's energy and inner cross fields and
+  // this lane's E_I entry are read first, unconditionally (the record's
+  // unused fields are zero), so that their latency overlaps the tile rows'
+  // instead of following it one load at a time: [0] lane-bit energy, [1 + u]
+  // inner cross field u.  The other walks read them where they are used (their
+  // step loops hold 64-entry tables, and longer-lived set-up values spill).
   const gptr<const W> lt = gp((const W*)v.lt) + ((int64_t)b * 64 + lane) * kLaneRec;
   W lrec[7];
+  if constexpr (kLaneEI) {
 #pragma unroll
-  for (int i = 0; i < 7; ++i) lrec[i] = lt[i];
+    for (int i = 0; i < 7; ++i) lrec[i] = lt[i];
+  }
   const W eil = (kLaneEI && lane < NB) ? ei[lane] : (W)0;
   // tile sums: S (lane t < tp0) = sum_{set tile bits k} S(t, tp0+k);
   // R (tile row t = lane, bit t set) = sum_{set tile bits k >= t} Q(tp0+t, tp0+k)
@@ -322,6 +326,11 @@ __device__ __forceinline__ typename Ar<E>::W lane_init_with(const Views& v, int 
   else etile = (W)uniform_u64((uint64_t)etile);
   myc[kTileRow * kWave + lane] = S;
   // lane record + tile sums
+  if constexpr (!kLaneEI) {
+    lrec[0] = lt[0];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) lrec[1 + u] = u < I.B ? lt[1 + u] : (W)0;
+  }
   W EP = etile + lrec[0];
   for (int a = 0; a < I.L; ++a)
     if ((lane >> a) & 1) EP += myc[kTileRow * kWave + pos0 + a];
@@ -331,13 +340,15 @@ __device__ __forceinline__ typename Ar<E>::W lane_init_with(const Views& v, int 
     cI[u] = u < I.B ? lrec[1 + u] + myc[kTileRow * kWave + u] : (W)0;
     myc[(kCIRow + u) * kWave + lane] = cI[u];
   }
-  {  // outer cross fields: all loads in flight together, then the stores
+  if constexpr (kLaneEI) {  // outer cross fields: all loads in flight together, then the stores
     W lo[kMaxOuter];
 #pragma unroll
     for (int l = 0; l < kMaxOuter; ++l) lo[l] = lt[8 + l];
 #pragma unroll
     for (int l = 0; l < kMaxOuter; ++l)
       if (l < I.no) myc[l * kWave + lane] = lo[l] + myc[kTileRow * kWave + I.B + l];
+  } else {
+    for (int l = 0; l < I.no; ++l) myc[l * kWave + lane] = lt[8 + l] + myc[kTileRow * kWave + I.B + l];
   }
   // kLaneEI: lane j loaded E_I(j) above (one coalesced load) and the loop
   // reads it back by lane, for kernels at 128 VGPRs where 64 entries loaded

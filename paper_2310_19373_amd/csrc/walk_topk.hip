@@ -119,7 +119,6 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
 
-  const double g0 = load_gthr(v, b);  // issued first: its latency overlaps the set-up's
   // ---- lane init: prefix energy, inner table, outer cross fields
   E C[NB];
   const W EP = lane_init<E, NB>(v, b, I, local, valid, myc, lane, C);
@@ -131,6 +130,7 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
   using Acc = std::conditional_t<kInt, int32_t, double>;
   // pub also tracks the lowest threshold seen, so a wave publishes (one
   // atomic) only a value below what the instance already has
+  const double g0 = load_gthr(v, b);
   if (enc_key(g0) < pub) pub = enc_key(g0);
   double thr = fmin(fmin(g0, I.big), readlane_f64(lkey, I.kp - 1));
   Acc Dp = kInt ? (Acc)((int32_t)thr - (int32_t)EP) : (Acc)(thr - (double)EP);
