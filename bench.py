@@ -38,11 +38,14 @@ sys.path.insert(0, ROOT)
 # float32 screen (and the int32 walk): one table addition (v_add_f32 with a DPP
 # row broadcast) plus half of a three-input minimum (v_min3_f32 folds two
 # states).  Half-precision screen (the float32 default): per block of 64 states
-# 32 v_pk_add_f16 (two states each) for C' + Tb, 30 v_pk_min_f16 for the
-# minimum over b, 2 v_pk_add_f16 for + Ta, 1 v_pk_min_f16 and 1 v_min_f16 for
-# the minimum over a: 66 / 64.
+# 32 v_pk_add_f16 (two states each) for C' + Tb, 14 three-input
+# v_pk_minimum3_f16 and 2 v_pk_min_f16 for the minimum over b, 2 v_pk_add_f16
+# for + Ta, 1 v_pk_minimum3_f16 and 1 v_min_f16 for the minimum over a:
+# 52 / 64.  The int16 screen (int32 Q) has no three-input packed minimum:
+# 32 v_pk_add_i16, 30 v_pk_min_i16, 2 v_pk_add_i16, 2 minimums: 66 / 64.
 ALG_OPS_PER_STATE = 1.5
-HALF_OPS_PER_STATE = 66 / 64
+HALF_OPS_PER_STATE = 52 / 64
+INT16_OPS_PER_STATE = 66 / 64
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 non-packed VALU lane-ops/s.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
@@ -150,12 +153,21 @@ def float_ops_per_state(wide: bool = False):
     return 3.0 if wide else ALG_OPS_PER_STATE
 
 
+def int32_ops_per_state():
+    """Lane-ops per state of the int32 walk: the int16 screen's when the half
+    screens are on (int32 Q whose inner rows fit int16), else the int32
+    screen's 1.5."""
+    from paper_2310_19373_amd import _lib
+
+    return INT16_OPS_PER_STATE if _lib.get_tuning(_lib.TUNE_HALF_SCREEN) > 0 else ALG_OPS_PER_STATE
+
+
 def extra_single(dev, name, Q, k, dt, reps, ops_per_state=ALG_OPS_PER_STATE):
     """One full qubo_bf_solve per call on another configuration; states/s of
     the call and the walk kernel's VALU roofline fraction (ops_per_state
-    lane-ops per state: 66/64 for the half screen, 1.5 for the float32 and
-    int32 screens, 3 for the float64 walk's; HIP events around the walk
-    launch)."""
+    lane-ops per state: 52/64 for the float16 screen, 66/64 for the int16
+    screen, 1.5 for the float32 and int32 screens, 3 for the float64 walk's;
+    HIP events around the walk launch)."""
     import torch
 
     from paper_2310_19373_amd import _lib
@@ -433,7 +445,7 @@ def main():
             res = leg_batched(dev, plain_loop=False, tune=not args.no_tune)
         elif args.only == "n32_i32":
             res = extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16", inputs.single_n32_i32(), 16,
-                               _lib.QUBO_I32, 10, ops_per_state=float_ops_per_state())
+                               _lib.QUBO_I32, 10, ops_per_state=int32_ops_per_state())
         elif args.only == "n40_f64":
             res = extra_single(dev, "n=40 planted (seed 2) as float64 Q, k=16",
                                inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64, 3,
@@ -551,7 +563,7 @@ def main():
                                            _lib.QUBO_F32, 50, ops_per_state=float_ops_per_state()),
             "single_n32_i32": extra_single(dev, "n=32 int32 uniform [-100,100] (seed 1), k=16",
                                            inputs.single_n32_i32(), 16, _lib.QUBO_I32, 10,
-                                           ops_per_state=float_ops_per_state()),
+                                           ops_per_state=int32_ops_per_state()),
             "single_n40_f64": extra_single(dev, "n=40 planted (seed 2) as float64 Q, k=16",
                                            inputs.single_n40_f32_planted()[0].astype("float64"), 16, _lib.QUBO_F64,
                                            3, ops_per_state=float_ops_per_state(wide=True)),

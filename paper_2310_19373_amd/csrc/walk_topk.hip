@@ -271,18 +271,26 @@ __device__ __forceinline__ void walk_unit(const Views& v, int b, const InstU& I,
 // values,
 //   m = min_a [ Ta(a) + min_b (C'(b | a << 4) + Tb(b)) ]
 // with C' paired as (a, a + 2) per register: 32 v_pk_add_f16 (two states
-// each, Tb(b) taken from either half of a scalar register by op_sel),
-// 30 v_pk_min_f16, 2 v_pk_add_f16 for + Ta and 2 minimums: 66 instructions
-// for 64 states.  The float64 offset Dp is kept scaled by hscale (exact: a
-// power of two), and the block passes when m <= Dp - tau, tau = hscale E_O -
-// hmargin.  hmargin makes the half screen pass every block the float32 (or
-// float64) screen passes; the replay recomputes passing blocks with exact
-// keys.
+// each, Tb(b) taken from either half of a scalar register by op_sel), 16
+// three-input v_pk_minimum3_f16 and 2 v_pk_min_f16 folding each 16-register
+// group, 2 v_pk_add_f16 for + Ta and 2 final minimums: 52 instructions for 64
+// states.  The operands are finite or +inf (every scaled table value is below
+// 2^13 in magnitude, unused states are +inf), so no NaN reaches the IEEE
+// minimum and it selects the same value as the ordinary minimum.  The float64
+// offset Dp is kept scaled by hscale (exact: a power of two), and the block
+// passes when m <= Dp - tau, tau = hscale E_O - hmargin.  hmargin makes the
+// half screen pass every block the float32 (or float64) screen passes; the
+// replay recomputes passing blocks with exact keys.
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(4))) uint32_t* half_words_t;
 
 __device__ __forceinline__ h2 as_h2(uint32_t x) { return __builtin_bit_cast(h2, x); }
 __device__ __forceinline__ h2 hmin2(h2 a, h2 b) { return __builtin_elementwise_min(a, b); }
+// one v_pk_minimum3_f16
+__device__ __forceinline__ h2 hmin3(h2 a, h2 b, h2 c) {
+  return __builtin_elementwise_minimum(__builtin_elementwise_minimum(a, b), c);
+}
+__device__ __forceinline__ h2 hswap(h2 x) { return __builtin_shufflevector(x, x, 1, 0); }
 
 __device__ __forceinline__ float half_block_min(const HalfRow& r, const h2 (&C)[2][16]) {
   h2 m[2];
@@ -294,15 +302,16 @@ __device__ __forceinline__ float half_block_min(const HalfRow& r, const h2 (&C)[
       const h2 x = as_h2(r.tb[c >> 1]);
       s[c] = C[a][c] + ((c & 1) ? __builtin_shufflevector(x, x, 1, 1) : __builtin_shufflevector(x, x, 0, 0));
     }
+    // 16 -> 6 -> 2 -> 1
+    h2 t[6];
 #pragma unroll
-    for (int w = 8; w > 0; w >>= 1)
-#pragma unroll
-      for (int c = 0; c < w; ++c) s[c] = hmin2(s[c], s[c + w]);
-    m[a] = s[0] + as_h2(r.ta[a]);
+    for (int i = 0; i < 5; ++i) t[i] = hmin3(s[3 * i], s[3 * i + 1], s[3 * i + 2]);
+    t[5] = s[15];
+    m[a] = hmin2(hmin3(t[0], t[1], t[2]), hmin3(t[3], t[4], t[5])) + as_h2(r.ta[a]);
   }
-  m[0] = hmin2(m[0], m[1]);
-  const h2 f = hmin2(m[0], __builtin_shufflevector(m[0], m[0], 1, 0));
-  return (float)f.x;
+  // x.x = min(m0.x, m1.x, m1.y), x.y = min(m0.y, m1.y, m1.x): together all four
+  const h2 x = hmin3(m[0], m[1], hswap(m[1]));
+  return (float)hmin2(x, hswap(x)).x;
 }
 
 // Waits for every scalar-memory / LDS result in flight (the row of the step

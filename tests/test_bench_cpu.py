@@ -51,7 +51,9 @@ def test_committed_counters_name_their_sources():
 
 
 def test_algorithmic_work_per_state():
-    # 66 packed instructions per 64 states for the half screen; 1.5 per state
-    # (one DPP add, half a three-input minimum) for the float32 screen
-    assert bench.HALF_OPS_PER_STATE == 66 / 64
+    # 52 packed instructions per 64 states for the float16 screen, 66 for the
+    # int16 screen; 1.5 per state (one DPP add, half a three-input minimum)
+    # for the float32 screen
+    assert bench.HALF_OPS_PER_STATE == 52 / 64
+    assert bench.INT16_OPS_PER_STATE == 66 / 64
     assert bench.ALG_OPS_PER_STATE == 1.5
