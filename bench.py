@@ -399,6 +399,31 @@ def leg_logz(dev, plain_loop=True):
     return out
 
 
+def valu_rates():
+    """Cycles per wave64 VALU instruction per SIMD for each instruction form of
+    the walks (the probe library built beside the solver; the shader clock is
+    read in the same launch).  One JSON line per form and occupancy."""
+    import ctypes
+
+    path = os.path.join(ROOT, "paper_2310_19373_amd", "libvalu_rates.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    P = ctypes.CDLL(path)
+    P.valu_rate.restype = ctypes.c_int
+    P.valu_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    P.valu_rate_form_name.restype = ctypes.c_char_p
+    for wps in (4, 8):
+        for form in range(P.valu_rate_forms()):
+            ms, mhz, cyc = ctypes.c_float(), ctypes.c_double(), ctypes.c_double()
+            rc = P.valu_rate(form, wps, 20000, ctypes.byref(ms), ctypes.byref(mhz), ctypes.byref(cyc))
+            if rc != 0:
+                raise RuntimeError(f"valu_rate({form}, {wps}) returned {rc}")
+            print(json.dumps({"form": P.valu_rate_form_name(form).decode(), "waves_per_simd": wps,
+                              "ms": round(ms.value, 4), "shader_mhz": round(mhz.value, 1),
+                              "cycles_per_instr": round(cyc.value, 3)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,9 +441,15 @@ def main():
     ap.add_argument("--sources-sha", action="store_true", help="print the walk sources' sha256 and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (counter calibration for HBM bytes)")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="run only the VALU issue-cost probe: cycles per wave64 instruction of each form the "
+                         "walks use, at 4 and 8 waves per SIMD")
     args = ap.parse_args()
     if args.sources_sha:
         print(walk_sources_sha256())
+        return
+    if args.valu_rates:
+        valu_rates()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one device; "

@@ -20,6 +20,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqubo_bf.so")
+# measurement tool beside the library: issue cost of the VALU forms the walks use
+PROBE_SRC = os.path.join(CSRC, "probe", "valu_rates.hip")
+PROBE_LIB = os.path.join(PKG, "libvalu_rates.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -56,6 +59,9 @@ def build(verbose: bool = False, save_temps: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp"
+    _run([HIPCC, *FLAGS, "-shared", "-o", tmp, PROBE_SRC], verbose)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 
