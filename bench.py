@@ -259,12 +259,16 @@ def extra_sample(dev, nsamples=256):
             "ms": t * 1e3, "samples_per_s": Q.shape[0] * nsamples / t}
 
 
-# Algorithmic lane-ops per state of the log-partition walks (factored form):
-# forward, one DPP-broadcast FMA per state plus one exp2 per 64-state block;
-# adjoint, one DPP-broadcast multiply (the weight), one FMA into the inner
-# moment W[j] and the pairwise tree for s and v_a (62 additions per 32 states).
-LOGZ_FWD_OPS_PER_STATE = 1 + 1 / 64
-LOGZ_BWD_OPS_PER_STATE = 2 + 62 / 32
+# Algorithmic work per state of the log-partition walks (factored form), in
+# issue slots of the 4-cycle VALU rate the peak counts: forward, one
+# DPP-broadcast FMA per state (one slot) plus one exp2 per 64-state block (two
+# slots: v_exp_f32 issues once per 8 cycles); adjoint, per 32 states, 32
+# DPP-broadcast multiplies (the weights, one slot each), 32 FMAs into the
+# inner moments W[j] and the 62 additions of the pairwise tree for s and v_a
+# (VGPR-only float32 forms, which issue twice as fast: half a slot each) and
+# one exp2.
+LOGZ_FWD_OPS_PER_STATE = (64 + 2) / 64
+LOGZ_BWD_OPS_PER_STATE = (32 + 32 / 2 + 62 / 2 + 2) / 32
 
 
 def leg_batched(dev, plain_loop=True, tune=True):
