@@ -259,15 +259,16 @@ def extra_sample(dev, nsamples=256):
             "ms": t * 1e3, "samples_per_s": Q.shape[0] * nsamples / t}
 
 
-# Algorithmic work per state of the log-partition walks (factored form), in
-# issue slots of the 4-cycle VALU rate the peak counts: forward, one
-# DPP-broadcast FMA per state (one slot) plus one exp2 per 64-state block (two
-# slots: v_exp_f32 issues once per 8 cycles); adjoint, per 32 states, 32
-# DPP-broadcast multiplies (the weights, one slot each), 32 FMAs into the
-# inner moments W[j] and the 62 additions of the pairwise tree for s and v_a
-# (VGPR-only float32 forms, which issue twice as fast: half a slot each) and
-# one exp2.
-LOGZ_FWD_OPS_PER_STATE = (64 + 2) / 64
+# Algorithmic work per state of the log-partition walks (factored form).
+# Forward: on the matrix cores, one multiply-add per state (the product U +=
+# B_t^T G_t of step-factor rows and per-lane step weights), 2 flops against
+# the float32 matrix peak.  Adjoint: in issue slots of the 4-cycle VALU rate
+# the VALU peak counts: per 32 states, 32 DPP-broadcast multiplies (the
+# weights, one slot each), 32 FMAs into the inner moments W[j] and the 62
+# additions of the pairwise tree for s and v_a (VGPR-only float32 forms,
+# which issue twice as fast: half a slot each) and one exp2 (two slots).
+LOGZ_FWD_FLOPS_PER_STATE = 2
+PEAK_MFMA_F32 = 157.3e12  # MI355X dense float32 matrix peak, FLOP/s
 LOGZ_BWD_OPS_PER_STATE = (32 + 32 / 2 + 62 / 2 + 2) / 32
 
 
@@ -382,8 +383,9 @@ def leg_logz(dev, plain_loop=True):
     bwd_s = kern["walk_grad"][0] / 1e3 / max(kern["walk_grad"][1], 1)
     out = {"workload": "768 (instance, beta) pairs: 256 QUBOs n=24 float32 N(0,1/n) (seed 4) x beta {0.5,1,4}",
            "states_per_pass": states, "batched_fwd_bwd_ms": t_batched * 1e3,
-           "kernels": {"walk_exp_fac_kernel": {"ms": fwd_s * 1e3, "ops_per_state": LOGZ_FWD_OPS_PER_STATE,
-                                               "frac": states * LOGZ_FWD_OPS_PER_STATE / fwd_s / PEAK_LANE_OPS},
+           "kernels": {"walk_exp_fac_kernel": {"ms": fwd_s * 1e3, "bound": "mfma",
+                                               "flops_per_state": LOGZ_FWD_FLOPS_PER_STATE,
+                                               "frac": states * LOGZ_FWD_FLOPS_PER_STATE / fwd_s / PEAK_MFMA_F32},
                        "walk_grad_fac_kernel": {"ms": bwd_s * 1e3, "ops_per_state": LOGZ_BWD_OPS_PER_STATE,
                                                 "frac": states * LOGZ_BWD_OPS_PER_STATE / bwd_s / PEAK_LANE_OPS}}}
     if plain_loop:

@@ -45,6 +45,17 @@ constexpr int kGradStates = 1 << kGradInner;
 constexpr int kGradMaxOuter = 8;
 constexpr int kSampleOuter = 8;  // outer bits of the sampling plan (block weights fit in LDS)
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Exchanges the upper 32 lanes of x with the lower 32 lanes of y:
+//   x <- [x(0..31), y(0..31)],  y <- [x(32..63), y(32..63)].
+// Written as inline asm: this compiler's __builtin_amdgcn_permlane32_swap can
+// hand back the first result for both.  The nops cover the VALU-write /
+// permlane-read and permlane-write / VALU-or-MFMA-read hazards.
+__device__ __forceinline__ void half_swap(float& x, float& y) {
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+}
+
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -72,62 +83,6 @@ __device__ __forceinline__ void block_exp(float (&acc)[4], float t, const float*
   const float e = row_bcast<Q>(t) + C[16 * K + Q];
   acc[Q & 3] += exp2_fast(__builtin_fmaf(e, nb, cst));
   if constexpr (Q + 1 < 16) block_exp<K, Q + 1>(acc, t, C, nb, cst);
-}
-
-// acc[Q&3] += a(16K+Q) * b(16K+Q) for Q = 0..15, b broadcast from lane Q of
-// each 16-lane row: one v_fmac_f32 with a DPP row broadcast per state (the
-// compiler does not fold the broadcast into an FMA by itself).  The DPP
-// source t may have been written by the VALU just before, which needs two
-// wait states before a DPP read: hence the s_nop.
-template <int K>
-__device__ __forceinline__ void block_dot(float (&acc)[4], float t, const float* A) {
-  asm("s_nop 1\n"
-      "v_fmac_f32_dpp %0, %4, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %8 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %0, %4, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %10 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %11 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %12 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %0, %4, %13 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %15 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %0, %4, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %20 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
-      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])
-      : "v"(t), "v"(A[16 * K + 0]), "v"(A[16 * K + 1]), "v"(A[16 * K + 2]), "v"(A[16 * K + 3]),
-        "v"(A[16 * K + 4]), "v"(A[16 * K + 5]), "v"(A[16 * K + 6]), "v"(A[16 * K + 7]), "v"(A[16 * K + 8]),
-        "v"(A[16 * K + 9]), "v"(A[16 * K + 10]), "v"(A[16 * K + 11]), "v"(A[16 * K + 12]),
-        "v"(A[16 * K + 13]), "v"(A[16 * K + 14]), "v"(A[16 * K + 15]));
-}
-
-// As block_dot for K = 0, but the first four states start the accumulators
-// (v_mul_f32 instead of zeroing them and accumulating).
-__device__ __forceinline__ void block_dot_first(float (&acc)[4], float t, const float* A) {
-  asm("s_nop 1\n"
-      "v_mul_f32_dpp %0, %4, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
-      "v_mul_f32_dpp %1, %4, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
-      "v_mul_f32_dpp %2, %4, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
-      "v_mul_f32_dpp %3, %4, %8 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %0, %4, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %10 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %11 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %12 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %0, %4, %13 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %15 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %0, %4, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %1, %4, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %2, %4, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
-      "v_fmac_f32_dpp %3, %4, %20 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
-      : "=&v"(acc[0]), "=&v"(acc[1]), "=&v"(acc[2]), "=&v"(acc[3])
-      : "v"(t), "v"(A[0]), "v"(A[1]), "v"(A[2]), "v"(A[3]), "v"(A[4]), "v"(A[5]), "v"(A[6]), "v"(A[7]), "v"(A[8]),
-        "v"(A[9]), "v"(A[10]), "v"(A[11]), "v"(A[12]), "v"(A[13]), "v"(A[14]), "v"(A[15]));
 }
 
 // Per-lane range of the finite entries of C' and the factored-form decision
@@ -234,15 +189,38 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
         continue;
       }
       to_factors(C, bbf, cmin);
+      // The step sums are a matrix product on the matrix cores.  With g(l, t) =
+      // 2^(ntau(t) + P_l(t)) the lane's weight of step t, the lane's sum is
+      //   S_l = sum_j a(l, j) U(l, j),   U(l, j) = sum_t g(l, t) b(t, j),
+      // and U^T (64 inner states x 64 lanes) += B_t^T G_t over pairs of steps
+      // is four v_mfma_f32_32x32x2_f32 (inner half r x lane half c).  Result
+      // layout: lane q, register e of tile (c, r) holds U(32c + q%32, 32r + i)
+      // with i = (e%4) + 4 (q/32) + 8 (e/4).  Every 16 steps, at a reference
+      // move and at the unit's end, U is folded into S: lane q multiplies its
+      // entries by the matching a(l, j) (held in the same layout, AD) and
+      // swaps halves with lane q^32 to collect its own row.
       const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(gp((const float*)v.etab) + I.tab_off * kInnerStates), (short)0,
           (int)(steps * (uint32_t)(kInnerStates * sizeof(float))), 0x00020000);
-      // Exponents in units of bb: step t's block factor is 2^(ntau(t) + P),
-      // ntau(t) = -bb (min_j T' + E_O)(t) from the table, P = -bb (cm + K) +
-      // R the lane's part, R = bb r the lane's reference; a flip of outer bit
-      // l moves K by +-c_l, so P by -+bb c_l (the first three bits' products
-      // held in registers).  Block sums are accumulated in float32 over a
-      // group of eight steps (each at most 64 * 2^kRebase) and then in float64.
+      // AD[c][r][e] = a(32c + lane%32, 32r + i(e, lane)): the pair (a(j0), a(j0 + 4))
+      // of every lane, swapped across the wave halves
+      float AD[2][2][16];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int j0 = 32 * r + (e & 3) + 8 * (e >> 2);
+          AD[0][r][e] = C[j0];
+          AD[1][r][e] = C[j0 + 4];
+          half_swap(AD[0][r][e], AD[1][r][e]);
+        }
+      }
+      // Exponents in units of bb: step t's weight is 2^(ntau(t) + P), ntau(t) =
+      // -bb (min_j T' + E_O)(t) from the table, P = -bb (cm + K) + R the lane's
+      // part, R = bb r the lane's reference; a flip of outer bit l moves K by
+      // +-c_l, so P by -+bb c_l (the first three bits' products held in
+      // registers).  U holds at most 16 steps of weights (each at most
+      // 2^kRebase) before it is folded into the float64 sum.
       const gptr<const double> ntau = gp(v.tref) + I.tab_off;
       const double cm = (double)cmin;
       const double nt0 = ntau[0];
@@ -251,72 +229,140 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
       const double bc0 = I.no > 0 ? bb * myc[lane] : 0.0;
       const double bc1 = I.no > 1 ? bb * myc[kWave + lane] : 0.0;
       const double bc2 = I.no > 2 ? bb * myc[2 * kWave + lane] : 0.0;
-      float Sf = 0.f;
-      auto body = [&](const f32x4& bc, double nt) {
+      f32x16 U[2][2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) U[c][r] = f32x16{};
+      auto fold = [&]() {
+        // four chains of 8 products per lane half, summed pairwise
+        float pa[2][4] = {};
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            pa[0][e & 3] = __builtin_fmaf(AD[0][r][e], U[0][r][e], pa[0][e & 3]);
+            pa[1][e & 3] = __builtin_fmaf(AD[1][r][e], U[1][r][e], pa[1][e & 3]);
+          }
+        }
+        float p0 = (pa[0][0] + pa[0][1]) + (pa[0][2] + pa[0][3]);
+        float p1 = (pa[1][0] + pa[1][1]) + (pa[1][2] + pa[1][3]);
+        half_swap(p0, p1);
+        S += (double)(p0 + p1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int r = 0; r < 2; ++r) U[c][r] = f32x16{};
+      };
+      // The step's exponent after its flip.  A lane more than 2^kRebase above
+      // its reference first folds U (all lanes, uniform), then moves the
+      // reference by the exponent; `shift` returns that move (0 for the other
+      // lanes), by which a weight computed earlier but not yet in U is scaled.
+      auto expo = [&](double nt, double& shift) -> double {
         double ct = nt + P;
-        if (__builtin_expect(ballot(ct > kRebase) != 0, 0)) {  // rare: move the lane's reference
+        shift = 0.0;
+        if (__builtin_expect(ballot(ct > kRebase) != 0, 0)) {
+          fold();
           if (ct > kRebase) {
-            // S 2^-R is kept: the reference rises to the block's bound
-            S = (S + (double)Sf) * (double)exp2_fast((float)-ct);
-            Sf = 0.f;
+            S *= (double)exp2_fast((float)-ct);
             R -= ct;
             P -= ct;
+            shift = ct;
             ct = 0.0;
           }
         }
-        float acc[4];
-        block_dot_first(acc, bc.x, C);
-        block_dot<1>(acc, bc.y, C);
-        block_dot<2>(acc, bc.z, C);
-        block_dot<3>(acc, bc.w, C);
-        Sf = __builtin_fmaf((acc[0] + acc[1]) + (acc[2] + acc[3]), exp2_fast((float)ct), Sf);
+        return ct;
       };
-      auto load = [&](uint32_t t, f32x4& bv, double& nt) {
-        const uint32_t tt = t < steps ? t : steps - 1;
-        bv = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, qoff, (int)(tt * 256u), 0));
-        nt = ntau[tt];
+      // A operand of a pair of steps t0, t0 + 1: lane q holds b(t0 + q/32, 32r + q%32);
+      // entry j of a row sits at position 4 (j % 16) + j / 16
+      const int jl = lane & 31, tk = lane >> 5;
+      // lanes 32..63 read the pair's second row; both rows lie inside the
+      // table (t0 + 1 < steps, or a one-step walk, whose second row is its first)
+      const int boff0 = (4 * (jl & 15) + (jl >> 4)) * 4 + (steps > 1 ? tk * 256 : 0), boff1 = boff0 + 8;
+      auto loadb = [&](uint32_t t0, float& b0, float& b1) {
+        const int so = (int)((t0 + 1 < steps ? t0 : 0u) * 256u);
+        b0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brs, boff0, so, 0));
+        b1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brs, boff1, so, 0));
       };
-      f32x4 bn;
-      double nn;
-      load(0, bn, nn);
+      // one pair: the B operands (weights of both steps for the two lane
+      // halves) by a half swap, then the four MFMAs
+      auto mma = [&](float g0, float g1, float b0, float b1) {
+        float G0 = g0, G1 = g1;
+        half_swap(G0, G1);
+        U[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(b0, G0, U[0][0], 0, 0, 0);
+        U[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(b1, G0, U[0][1], 0, 0, 0);
+        U[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(b0, G1, U[1][0], 0, 0, 0);
+        U[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(b1, G1, U[1][1], 0, 0, 0);
+      };
+      auto weight = [&](double ct) { return valid ? exp2_fast((float)ct) : 0.f; };
       if (steps < 8) {
-        for (uint32_t t = 0; t < steps; ++t) {
-          const f32x4 bcur = bn;
-          const double ncur = nn;
-          load(t + 1, bn, nn);
+        // pairs of steps; the second step of a one-step walk has weight 0
+        for (uint32_t t = 0; t < steps; t += 2) {
+          float b0, b1;
+          loadb(t, b0, b1);
           if (t) {
             const int l = __builtin_ctz(t);
             P = __builtin_fma(((t >> (l + 1)) & 1) ? bb : -bb, myc[l * kWave + lane], P);
           }
-          body(bcur, ncur);
+          double sh0, sh1;
+          const double ct0 = expo(ntau[t], sh0);
+          float g0 = weight(ct0), g1 = 0.f;
+          if (t + 1 < steps) {
+            P = __builtin_fma((((t + 1) >> 1) & 1) ? bb : -bb, myc[lane], P);  // t + 1 flips bit 0
+            const double ct1 = expo(ntau[t + 1], sh1);
+            g0 = weight(ct0 - sh1);
+            g1 = weight(ct1);
+          }
+          mma(g0, g1, b0, b1);
         }
+        fold();
       } else {
         // groups of eight steps t = 8q + r: bit 0 turns on at r = 1, 5 and off
         // at 3, 7; bit 1 on at 2, off at 6; bit 2 at 4 (off for odd q); bit
-        // 3 + CTZ(q) at r = 0 (q > 0)
+        // 3 + CTZ(q) at r = 0 (q > 0).  Four pairs per group; U is folded every
+        // second group and at the end.
         const uint32_t groups = steps >> 3;
+        auto flip = [&](int r, uint32_t q) {
+          if (r == 0) {
+            if (q) {
+              const int l = 3 + __builtin_ctz(q);
+              P = __builtin_fma(((q >> (l - 2)) & 1) ? bb : -bb, myc[l * kWave + lane], P);
+            }
+          } else if (r == 1 || r == 5) {
+            P -= bc0;
+          } else if (r == 3 || r == 7) {
+            P += bc0;
+          } else if (r == 2) {
+            P -= bc1;
+          } else if (r == 6) {
+            P += bc1;
+          } else {
+            P += (q & 1) ? bc2 : -bc2;
+          }
+        };
+        float bn0, bn1;
+        loadb(0, bn0, bn1);
+        double nA = ntau[0], nB = ntau[1];
         for (uint32_t q = 0; q < groups; ++q) {
-          if (q) {
-            const int l = 3 + __builtin_ctz(q);
-            P = __builtin_fma(((q >> (l - 2)) & 1) ? bb : -bb, myc[l * kWave + lane], P);
-          }
 #pragma unroll
-          for (int rr = 0; rr < 8; ++rr) {
-            const f32x4 bcur = bn;
-            const double ncur = nn;
-            load(8 * q + rr + 1, bn, nn);
-            if (rr == 1 || rr == 5) P -= bc0;
-            else if (rr == 3 || rr == 7) P += bc0;
-            else if (rr == 2) P -= bc1;
-            else if (rr == 6) P += bc1;
-            else if (rr == 4) P += (q & 1) ? bc2 : -bc2;
-            body(bcur, ncur);
+          for (int pr = 0; pr < 4; ++pr) {
+            const uint32_t t0 = 8 * q + 2 * pr;
+            const float b0 = bn0, b1 = bn1;
+            const double n0 = nA, n1 = nB;
+            loadb(t0 + 2, bn0, bn1);  // the next pair's rows (rows 0, 1 past the end)
+            const uint32_t tn = t0 + 2 < steps ? t0 + 2 : steps - 2;
+            nA = ntau[tn];
+            nB = ntau[tn + 1];
+            double sh0, sh1;
+            flip(2 * pr, q);
+            const double ct0 = expo(n0, sh0);
+            flip(2 * pr + 1, q);
+            const double ct1 = expo(n1, sh1);
+            mma(weight(ct0 - sh1), weight(ct1), b0, b1);
           }
-          S += (double)Sf;
-          Sf = 0.f;
+          if ((q & 1) || q + 1 == groups) fold();
         }
       }
-      S += (double)Sf;
       lbias = R;
     } else {
       // direct form.  beta = 0: a tiny negative slope keeps the sentinel entries (+inf) at
@@ -368,7 +414,7 @@ __device__ __forceinline__ void walk_exp_body(const Views& v, const float* beta)
   }
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_exp_fac_kernel(Views v,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_exp_fac_kernel(Views v,
                                                                                             const float* beta) {
   walk_exp_body<0>(v, beta);
 }

@@ -3,8 +3,11 @@
 Tolerances (derived from the float32 walk arithmetic; u = 2^-24):
   logZ: each state's exponent is formed from float32 table values and a float32
   fma, so its error is at most about 3u*|beta|*sum|Q| (table rounding, the
-  sum and the per-step constant) plus exp2 and summation error (< 1e-6
-  relative); the test allows |dlogZ| <= 2e-6 + 4e-7 * |beta| * sum|Q|.
+  sum and the per-step constant); the weights are summed in float32 over at
+  most 16 steps per entry (matrix-core accumulation), folded in chains of 8
+  products summed pairwise, then in float64: at most about 26u ~ 1.6e-6
+  relative, all terms positive, plus exp2's error.  The test allows
+  |dlogZ| <= 2e-6 + 4e-7 * |beta| * sum|Q|.
   gradient: max-norm relative error <= 1e-4 against the float64 oracle.
 """
 import json
