@@ -284,8 +284,9 @@ const char* qubo_version(void);
  *   QUBO_TUNE_BATCHED_OUTER_BITS  max outer bits per work unit, batched / logZ
  *   QUBO_TUNE_WAVES_PER_CU        resident waves per compute unit of the walk grid
  *                                 (0, the default, reads back as 0 and means
- *                                 16 for the half-screen walk of float32,
- *                                 float64 and int64 Q, 12 otherwise); never
+ *                                 16 for the half-screen walks (float16
+ *                                 screen: float32, float64, int64 Q; int16
+ *                                 screen: int32 Q), 12 otherwise); never
  *                                 more than the walk kernel keeps resident
  *   QUBO_TUNE_KPRIME              candidate list length override (float path;
  *                                 values below k make the certificate fail)

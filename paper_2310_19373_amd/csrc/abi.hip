@@ -43,7 +43,7 @@ struct Tuning {
   int single_outer = 12;
   int single_unit = 14;
   int batched_outer = 9;
-  int waves_per_cu = 0;  // 0: 16 for the half-screen walk, 12 for the others
+  int waves_per_cu = 0;  // 0: 16 for the half-screen walks, 12 for the others
   int kprime = 0;
   int chunk_single = 2;
   int chunk_batched = 2;
@@ -349,7 +349,7 @@ int run_topk(const Views& v0, const void* Q, int64_t ldq, int64_t stride, const 
   const bool half = tuning().half_screen > 0 && pp.inner == kInner;
   v.h16 = half ? 1 : 0;
   // the half-screen walk (float32, float64 and int64 Q) runs 4 waves per SIMD
-  int waves = grid_waves(v.h16 && dt != kDtI32 ? 16 : 12, walk_topk_blocks_per_cu(dt, v.h16));
+  int waves = grid_waves(v.h16 ? 16 : 12, walk_topk_blocks_per_cu(dt, v.h16));
   if (units_hint > 0 && units_hint < waves) {
     waves = (int)units_hint;
     waves += (kWavesPerBlock - waves % kWavesPerBlock) % kWavesPerBlock;

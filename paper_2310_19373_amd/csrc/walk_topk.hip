@@ -702,14 +702,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) walk_topk_f64_kernel(Views v) {
   walk_topk_body<double, false>(v);
 }
-// The half-screen walk keeps its step loop within 128 VGPRs (its rows are in
-// scalar registers, C' is 32 packed pairs), so it runs 4 waves per SIMD: the
-// extra wave hides the scalar row loads and unit set-up (n=40 1.5 % faster,
-// the 4096-instance batch 6 %); the set-up and replay paths spill.
+// The half-screen walks keep their step loops within 128 VGPRs (the rows are
+// in scalar registers, C' is 32 packed pairs), so they run 4 waves per SIMD:
+// the extra wave hides the scalar row loads, unit set-up and the serial tail
+// of each step's minimum tree (float16: n=40 1.5 % faster, the 4096-instance
+// batch 6 %; int16: n=32 int32 10 %); the set-up and replay paths spill.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) walk_topk_h16_kernel(Views v) {
   walk_topk_body<float, true>(v);
 }
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) walk_topk_i16_kernel(Views v) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) walk_topk_i16_kernel(Views v) {
   walk_topk_body<int32_t, true>(v);
 }
 
