@@ -549,36 +549,99 @@ __device__ __forceinline__ void block_prod8(float (&w)[kGradStates], float t, co
   }
 }
 
-// s = sum_j w_j and v_a = sum_j w_j j_a (a < 5) by a pairwise tree.
+// s = sum_j w_j and v_a = sum_j w_j j_a (a < 5), every sum a pairwise tree:
+// level a + 1 adds the pairs of level a (p, q, r, h), and v_a sums the odd
+// members of level a.  57 adds, at most five deep.
+template <int N>
+__device__ __forceinline__ float tree_sum(const float* x) {
+  if constexpr (N == 1) return x[0];
+  else return tree_sum<N / 2>(x) + tree_sum<N / 2>(x + N / 2);
+}
 __device__ __forceinline__ void block_moments(const float (&w)[kGradStates], float& s, float (&va)[kGradInner]) {
-  float lvl[16];
-#pragma unroll
-  for (int a = 0; a < kGradInner; ++a) va[a] = 0.f;
+  static_assert(kGradInner == 5, "five inner bits");
+  float p[16], o[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    lvl[i] = w[2 * i] + w[2 * i + 1];
-    va[0] += w[2 * i + 1];
+    p[i] = w[2 * i] + w[2 * i + 1];
+    o[i] = w[2 * i + 1];
   }
-  int len = 16;
+  va[0] = tree_sum<16>(o);
+  float q[8];
 #pragma unroll
-  for (int a = 1; a < kGradInner; ++a) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (i < len / 2) {
-        va[a] += lvl[2 * i + 1];
-        lvl[i] = lvl[2 * i] + lvl[2 * i + 1];
-      }
-    }
-    len /= 2;
+  for (int i = 0; i < 8; ++i) {
+    q[i] = p[2 * i] + p[2 * i + 1];
+    o[i] = p[2 * i + 1];
   }
-  s = lvl[0];
+  va[1] = tree_sum<8>(o);
+  float r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = q[2 * i] + q[2 * i + 1];
+    o[i] = q[2 * i + 1];
+  }
+  va[2] = tree_sum<4>(o);
+  const float h0 = r[0] + r[1], h1 = r[2] + r[3];
+  va[3] = r[1] + r[3];
+  va[4] = h1;
+  s = h0 + h1;
 }
 
 __device__ __forceinline__ int pidx(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
+// The moments of a unit in the order the adjoint sums them: pairs of positions
+// (kind, index) with kind 0 an inner bit, 1 an outer bit, 2 a lane bit; kind 3
+// is the unit's total (kept for the pairs of two tile bits).  The table holds
+// every pair the largest plan has; a unit skips the ones its plan lacks.
+struct MomentSlot {
+  signed char k1, i1, k2, i2;
+};
+constexpr int kMomentSlots =
+    kGradInner * (kGradInner + 1) / 2 + kGradMaxOuter * kGradInner + kGradMaxOuter * (kGradMaxOuter + 1) / 2 +
+    6 * (kGradInner + kGradMaxOuter) + 21 + 1;
+constexpr int kTotalSlot = 31;  // stash slot of the total (positions use 0 .. 19)
+struct MomentTable {
+  MomentSlot s[kMomentSlots];
+};
+constexpr MomentTable make_moment_table() {
+  MomentTable t{};
+  int k = 0;
+  auto put = [&](int k1, int i1, int k2, int i2) {
+    t.s[k++] = MomentSlot{(signed char)k1, (signed char)i1, (signed char)k2, (signed char)i2};
+  };
+  for (int a = 0; a < kGradInner; ++a)
+    for (int a2 = a; a2 < kGradInner; ++a2) put(0, a, 0, a2);
+  for (int o = 0; o < kGradMaxOuter; ++o) {
+    for (int a = 0; a < kGradInner; ++a) put(0, a, 1, o);
+    for (int o2 = o; o2 < kGradMaxOuter; ++o2) put(1, o, 1, o2);
+  }
+  for (int ll = 0; ll < 6; ++ll) {
+    for (int a = 0; a < kGradInner; ++a) put(0, a, 2, ll);
+    for (int o = 0; o < kGradMaxOuter; ++o) put(1, o, 2, ll);
+    for (int l2 = 0; l2 <= ll; ++l2) put(2, l2, 2, ll);
+  }
+  put(3, 0, 3, 0);
+  return t;
+}
+constexpr MomentTable kMomentTable = make_moment_table();
+static_assert(kMomentTable.s[kMomentSlots - 1].k1 == 3 && kMomentTable.s[kMomentSlots - 2].k1 == 2,
+              "the table fills every slot");
+__constant__ MomentTable kMomentTableDev = kMomentTable;
+
+// f(std::integral_constant<int, S>) for S = 0 .. N-1, in order.
+template <int N, int S = 0>
+struct Unrolled {
+  template <class F>
+  static __device__ __forceinline__ void run(F&& f) {
+    if constexpr (S < N) {
+      f(std::integral_constant<int, S>{});
+      Unrolled<N, S + 1>::run(f);
+    }
+  }
+};
+
 template <int PASS>
 __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta, const double* logz, int npairs) {
-  __shared__ double ctab[kWavesPerBlock][kWaveRows * kWave];
+  __shared__ __attribute__((aligned(16))) double ctab[kWavesPerBlock][kWaveRows * kWave];
   const int lane = threadIdx.x & 63;
   double* myc = ctab[threadIdx.x >> 6];
   const uint64_t total_units = uniform_u64(gp((const Header*)v.hdr)->total_units);
@@ -614,9 +677,20 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
         (int)(steps * (uint32_t)(kGradStates * sizeof(float))), 0x00020000);
     const gptr<const double> tref = gp(v.tref) + I.tab_off;
 
+    // inner x inner: the direct form sums W[j] = sum_t w(t, j) per lane; the
+    // factored form sums U(j, l) = sum_t g(l, t) b(t, j) on the matrix cores
+    // (W = a_j U at the end, as in the forward): U^T (32 inner states x 64
+    // lanes, two 32 x 32 tiles, one per lane half) += B^T G over pairs of
+    // steps, with v_mfma_f32_32x32x2_f32.  Tile c, lane q, element e holds
+    // inner state (e%4) + 4 (q/32) + 8 (e/4) of lane 32 c + q%32.
     float W[kGradStates];
 #pragma unroll
     for (int j = 0; j < kGradStates; ++j) W[j] = 0.f;
+    f32x16 U[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) U[c][e] = 0.f;
     // A[o][0] = sum_t x_o(t) s(t), A[o][1 + a] = sum_t x_o(t) v_a(t),
     // Bo[hi (hi - 1) / 2 + lo] = sum_t x_lo(t) x_hi(t) s(t)
     float A[kGradMaxOuter][kGradInner + 1];
@@ -634,28 +708,30 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
     // holds the step's -bb (min_j T' + E_O).
     const double cm = (double)cmin;
     double K = EP;
-    double Pg = -bb * (cm + EP) - lz2;
+    // a lane without states (beyond the instance's lane bits) gets g = 0
+    double Pg = valid ? -bb * (cm + EP) - lz2 : -__builtin_inf();
     // Block sums of one step: y[0] = s = sum_j w(t, j), y[1 + a] = v_a =
-    // sum_j w(t, j) j_a; W[j] += w(t, j).  The caller has moved K / Pg to step t.
+    // sum_j w(t, j) j_a; direct form: W[j] += w(t, j); factored form: the
+    // step factor g in gs.  The caller has moved K / Pg to step t.
     const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_body
-    auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1]) {
+    auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1], float& gs) {
       float w[kGradStates];
       float va[kGradInner];
       if constexpr (decltype(fc)::value) {
         // sc = -bb (min_j T' + E_O)(t); weight = g * a_j * b(t, j) <= 1, g <= 2^kSafeExp2
         const float g = exp2_fast((float)(sc + Pg));
+        gs = g;
         block_prod8<0, 0>(w, tc.x, C);
         block_prod8<0, 1>(w, tc.x, C);
         block_prod8<1, 0>(w, tc.y, C);
         block_prod8<1, 1>(w, tc.y, C);
-#pragma unroll
-        for (int j = 0; j < kGradStates; ++j) W[j] = __builtin_fmaf(g, w[j], W[j]);
         block_moments(w, y[0], va);
         y[0] *= g;
 #pragma unroll
         for (int c = 0; c < kGradInner; ++c) y[1 + c] = va[c] * g;
       } else {
         // sc = E_O(g(t))
+        gs = 0.f;
         const float cst = (float)(-bb * (K + sc) - lz2);
         block_w<0, 0>(w, tc.x, C, nb, cst);
         block_w<1, 0>(w, tc.y, C, nb, cst);
@@ -679,10 +755,25 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
       if constexpr (fac) Pg = __builtin_fma(off ? bb : -bb, myc[l * kWave + lane], Pg);
       else K = __builtin_fma(off ? -1.0 : 1.0, myc[l * kWave + lane], K);
     };
+    // b(t, q%32) in lane q: the step row holds b(t, Q) and b(t, 16 + Q) in
+    // lane Q = q%16 (the DPP broadcast layout)
+    auto bsel = [&](const f32x2& tc) { return (lane & 16) ? tc.y : tc.x; };
+    // U^T += B^T G for steps t0, t0 + 1: the A operand (32 x 2) takes
+    // b(t0 + q/32, q%32) in lane q, the B operand (2 x 32) of tile c takes
+    // g(t0 + q/32) of lane 32 c + q%32, which one half-wave swap of (g0, g1)
+    // gives for both tiles.
+    auto mma = [&](float b0, float b1, float g0, float g1) {
+      const float av = (lane & 32) ? b1 : b0;
+      half_swap(g0, g1);
+      U[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g0, U[0], 0, 0, 0);
+      U[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g1, U[1], 0, 0, 0);
+    };
 
     auto walk = [&](auto fc) {
       if (steps < 8) {
-        // short walks: every step adds into the moments of its set bits
+        // short walks: every step adds into the moments of its set bits; a
+        // one-step walk pairs its step with a zero factor
+        float be = 0.f, ge = 0.f;
         for (uint32_t t = 0; t < steps; ++t) {
           const f32x2 tc = tn;
           const double sc = sn;
@@ -691,8 +782,19 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
             const int l = __builtin_ctz(t);
             kflip(l, (t >> (l + 1)) & 1);
           }
-          float y[kGradInner + 1];
-          block(fc, tc, sc, y);
+          float y[kGradInner + 1], g;
+          block(fc, tc, sc, y, g);
+          if constexpr (fac) {
+            const float bv = bsel(tc);
+            if (t & 1) {
+              mma(be, bv, ge, g);
+            } else if (t + 1 == steps) {
+              mma(bv, bv, g, 0.f);
+            } else {
+              be = bv;
+              ge = g;
+            }
+          }
           const uint32_t o = (uint32_t)gray(t);
   #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -754,6 +856,7 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
   #pragma unroll
           for (int c = 0; c <= kGradInner; ++c) F[c] = H[c] = 0.f;
           float s0f = 0.f, s0h = 0.f, s1f = 0.f, s1h = 0.f;  // s over bit-0 / bit-1 steps per half
+          float be = 0.f, ge = 0.f;                          // even step of the pair
   #pragma unroll
           for (int r = 0; r < 8; ++r) {
             const uint32_t t = 8 * q + r;
@@ -768,8 +871,17 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
               const int l = (r & 1) ? 0 : 1;
               kflip(l, r == 3 || r == 7 || r == 6);
             }
-            float y[kGradInner + 1];
-            block(fc, tc, sc, y);
+            float y[kGradInner + 1], g;
+            block(fc, tc, sc, y, g);
+            if constexpr (fac) {
+              const float bv = bsel(tc);
+              if (r & 1) {
+                mma(be, bv, ge, g);
+              } else {
+                be = bv;
+                ge = g;
+              }
+            }
             const bool b0 = r == 1 || r == 2 || r == 5 || r == 6;
             const bool b1 = r >= 2 && r <= 5;
   #pragma unroll
@@ -817,9 +929,28 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
       }
     };
     walk(std::integral_constant<bool, fac>{});
+    if constexpr (fac) {
+      // W[j] = a_j U(j, lane): a half-wave swap of the tiles' element e puts
+      // inner states (e%4) + 8 (e/4) and 4 more of the lane's own column in x, y
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        float x = U[0][e], y = U[1][e];
+        half_swap(x, y);
+        const int j0 = (e & 3) + 8 * (e >> 2);
+        W[j0] = C[j0] * x;
+        W[j0 + 4] = C[j0 + 4] * y;
+      }
+    }
 
     // ---- assemble the unit's moments sum_x w x_i x_j (i <= j)
-    const int n = I.n, B = I.B, no = I.no, pos0 = B + no;
+    // Each moment is the wave sum of one value per lane.  The values are summed
+    // 32 at a time through this wave's lane-field table in LDS (free once the
+    // walk is done): lane l stores its 32 values as row l, then sums column
+    // l%32 over the rows of its half-wave, and a half-wave swap adds the two
+    // halves.  Lane l%32 carries the tag of value l%32: its output index and
+    // its stash slot (the diagonals of the positions below the tile bits and
+    // the unit's total are kept for the pairs with a tile bit).
+    const int n = I.n, B = I.B, no = I.no, pos0 = B + no, L = I.L, m = pos0 + L;
     float st = 0.f, vt[kGradInner];
 #pragma unroll
     for (int a = 0; a < kGradInner; ++a) vt[a] = 0.f;
@@ -830,49 +961,80 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
       for (int a = 0; a < kGradInner; ++a)
         if ((j >> a) & 1) vt[a] += W[j];
     }
-    auto put = [&](int i, int j, float x) {
-      const double sum = (double)wave_sum(x);
-      if (lane == 0) out[pidx(n, i, j)] = sum;
-    };
-    // inner x inner
+    float* const rows = (float*)myc;
+    constexpr int kStride = 36;  // row stride in floats: 16-byte aligned rows, 4 banks apart
+    constexpr int kStash = kWave * kStride;
+    static_assert(kStash + 32 <= 2 * kWaveRows * kWave, "the rows fit the lane-field table");
+    // lane bit ll of the prefix (bit ll of the lane)
+    auto lbit = [&](int ll) { return valid && ((lane >> ll) & 1); };
+    float buf[32];
+    // chunk ch: lane l (l < 32) writes the wave sum of value 32 ch + l
+    auto flush = [&](int ch) {
+      f32x4* const row = (f32x4*)(rows + lane * kStride);
 #pragma unroll
-    for (int a = 0; a < kGradInner; ++a) {
-      if (a >= B) continue;
-      put(a, a, vt[a]);
+      for (int i = 0; i < 8; ++i) row[i] = f32x4{buf[4 * i], buf[4 * i + 1], buf[4 * i + 2], buf[4 * i + 3]};
+      float x[32];
 #pragma unroll
-      for (int a2 = a + 1; a2 < kGradInner; ++a2) {
-        if (a2 >= B) continue;
-        float x = 0.f;
-#pragma unroll
-        for (int j = 0; j < kGradStates; ++j)
-          if (((j >> a) & 1) && ((j >> a2) & 1)) x += W[j];
-        put(a, a2, x);
+      for (int i = 0; i < 32; ++i) x[i] = rows[((lane & 32) + i) * kStride + (lane & 31)];
+      float s = tree_sum<32>(x), t = s;
+      half_swap(s, t);
+      const float tot = s + t;
+      const int idx = 32 * ch + (lane & 31);
+      if (lane < 32 && idx < kMomentSlots) {
+        const MomentSlot e = kMomentTableDev.s[idx];
+        const int lim[3] = {B, no, L}, base[3] = {0, B, pos0};
+        if (e.k1 == 3) {
+          rows[kStash + kTotalSlot] = tot;
+        } else if (e.i1 < lim[e.k1] && e.i2 < lim[e.k2]) {
+          const int p1 = base[e.k1] + e.i1, p2 = base[e.k2] + e.i2;
+          out[pidx(n, p1, p2)] = (double)tot;
+          if (p1 == p2) rows[kStash + p1] = tot;
+        }
       }
-    }
-    // inner x outer, outer x outer
+    };
+    // value of slot S (the table's order), then the flush of a full chunk
+    Unrolled<kMomentSlots>::run([&](auto sc) {
+      constexpr int S = decltype(sc)::value;
+      constexpr MomentSlot e = kMomentTable.s[S];
+      float x;
+      if constexpr (e.k1 == 3) {
+        x = st;
+      } else if constexpr (e.k1 == 0 && e.k2 == 0) {
+        if constexpr (e.i1 == e.i2) {
+          x = vt[e.i1];
+        } else {
+          x = 0.f;
 #pragma unroll
-    for (int o = 0; o < kGradMaxOuter; ++o) {
-      if (o >= no) continue;
-#pragma unroll
-      for (int a = 0; a < kGradInner; ++a)
-        if (a < B) put(a, B + o, A[o][1 + a]);
-      put(B + o, B + o, A[o][0]);
-#pragma unroll
-      for (int o2 = o + 1; o2 < kGradMaxOuter; ++o2)
-        if (o2 < no) put(B + o, B + o2, Bo[o2 * (o2 - 1) / 2 + o]);
-    }
-    // pairs with a prefix bit (lane or tile bits of this lane's prefix p)
-    for (int c = pos0; c < n; ++c) {
-      const bool xc = valid && ((p >> (c - pos0)) & 1);
-#pragma unroll
-      for (int a = 0; a < kGradInner; ++a)
-        if (a < B) put(a, c, xc ? vt[a] : 0.f);
-#pragma unroll
-      for (int o = 0; o < kGradMaxOuter; ++o)
-        if (o < no) put(B + o, c, xc ? A[o][0] : 0.f);
-      for (int c2 = pos0; c2 <= c; ++c2) {
-        const bool x2 = (p >> (c2 - pos0)) & 1;
-        put(c2, c, (xc && x2) ? st : 0.f);
+          for (int j = 0; j < kGradStates; ++j)
+            if (((j >> e.i1) & 1) && ((j >> e.i2) & 1)) x += W[j];
+        }
+      } else if constexpr (e.k1 == 0 && e.k2 == 1) {
+        x = A[e.i2][1 + e.i1];
+      } else if constexpr (e.k1 == 1 && e.k2 == 1) {
+        if constexpr (e.i1 == e.i2) x = A[e.i1][0];
+        else x = Bo[e.i2 * (e.i2 - 1) / 2 + e.i1];
+      } else if constexpr (e.k1 == 0) {
+        x = lbit(e.i2) ? vt[e.i1] : 0.f;
+      } else if constexpr (e.k1 == 1) {
+        x = lbit(e.i2) ? A[e.i1][0] : 0.f;
+      } else {
+        x = (lbit(e.i2) && ((lane >> e.i1) & 1)) ? st : 0.f;
+      }
+      buf[S & 31] = x;
+      if constexpr ((S & 31) == 31 || S + 1 == kMomentSlots) flush(S >> 5);
+    });
+    // pairs with a tile bit: the bit is the same on every lane, so each such
+    // moment is its partner's diagonal sum (or, for two tile bits, the unit's
+    // total) or zero; lane i writes the pair (i, c)
+    if (m < n) {
+      const double dT = (double)rows[kStash + kTotalSlot];
+      const double dg = (double)rows[kStash + (lane < m ? lane : 0)];
+      for (int c = m; c < n; ++c) {
+        const bool xc = (local >> (c - m)) & 1;
+        if (lane <= c) {
+          const bool xi = lane < m || ((local >> ((lane - m) & 63)) & 1);
+          out[pidx(n, lane, c)] = (xc && xi) ? (lane < m ? dg : dT) : 0.0;
+        }
       }
     }
   }
