@@ -262,14 +262,16 @@ def extra_sample(dev, nsamples=256):
 # Algorithmic work per state of the log-partition walks (factored form).
 # Forward: on the matrix cores, one multiply-add per state (the product U +=
 # B_t^T G_t of step-factor rows and per-lane step weights), 2 flops against
-# the float32 matrix peak.  Adjoint: in issue slots of the 4-cycle VALU rate
-# the VALU peak counts: per 32 states, 32 DPP-broadcast multiplies (the
-# weights, one slot each), 32 FMAs into the inner moments W[j] and the 62
-# additions of the pairwise tree for s and v_a (VGPR-only float32 forms,
-# which issue twice as fast: half a slot each) and one exp2 (two slots).
+# the float32 matrix peak.  Adjoint (nested form, which every unit of the
+# workload takes): the inner sums W go to the matrix cores as in the forward;
+# on the VALU, in issue slots of the 4-cycle rate the VALU peak counts, per
+# 32 states: the 62 multiply-adds of the nested block sums s and v_a
+# (VGPR-only float32 forms, which issue twice as fast: half a slot each), 6
+# DPP row broadcasts of the step's factors (one slot each), one reciprocal and
+# one exp2 (two slots each).
 LOGZ_FWD_FLOPS_PER_STATE = 2
 PEAK_MFMA_F32 = 157.3e12  # MI355X dense float32 matrix peak, FLOP/s
-LOGZ_BWD_OPS_PER_STATE = (32 + 32 / 2 + 62 / 2 + 2) / 32
+LOGZ_BWD_OPS_PER_STATE = (62 / 2 + 6 + 2 + 2) / 32
 
 
 def leg_batched(dev, plain_loop=True, tune=True):

@@ -294,8 +294,12 @@ const char* qubo_version(void);
  *   QUBO_TUNE_CHUNK_BATCHED       work units per queue pull, batched / logZ
  *   QUBO_TUNE_DYNAMIC_QUEUE       1: atomic work queue; -1: static assignment
  *   QUBO_TUNE_LOGZ_FACTORED       1: log-partition walks may use the factored
- *                                 form (one FMA per state); -1: always one exp
- *                                 per state (same results within rounding)
+ *                                 form (one multiply-add per state), the
+ *                                 gradient walk its nested form where a unit's
+ *                                 step factors allow; 2: the factored form
+ *                                 with per-state products in the gradient
+ *                                 walk; -1: always one exp per state (same
+ *                                 results within rounding)
  *   QUBO_TUNE_SEED_SWEEPS         descent passes of the per-instance threshold
  *                                 seed before a top-k walk; -1: no seeding
  *                                 (speed only: results are identical)

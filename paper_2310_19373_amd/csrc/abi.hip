@@ -242,7 +242,7 @@ Views make_views(void* ws, const Layout& L, int batch, int nmax) {
   v.tref = L.tref ? (double*)(p + L.tref) : nullptr;
   v.dlist = L.dlist ? (uint64_t*)(p + L.dlist) : nullptr;
   v.lanepart = nullptr;
-  v.factor = L.etab && tuning().logz_factored > 0;
+  v.factor = L.etab ? clampi(tuning().logz_factored, 0, 2) : 0;
   v.seed_sweeps = tuning().seed_sweeps;
   v.batch = batch;
   v.nmax = nmax;
@@ -425,7 +425,7 @@ int qubo_bf_set_tuning(int knob, int value) {
     case QUBO_TUNE_CHUNK_SINGLE: t.chunk_single = value > 0 ? value : d.chunk_single; break;
     case QUBO_TUNE_CHUNK_BATCHED: t.chunk_batched = value > 0 ? value : d.chunk_batched; break;
     case QUBO_TUNE_DYNAMIC_QUEUE: t.dyn = value > 0 ? 1 : (value < 0 ? 0 : d.dyn); break;
-    case QUBO_TUNE_LOGZ_FACTORED: t.logz_factored = value > 0 ? 1 : (value < 0 ? 0 : d.logz_factored); break;
+    case QUBO_TUNE_LOGZ_FACTORED: t.logz_factored = value > 0 ? clampi(value, 1, 2) : (value < 0 ? 0 : d.logz_factored); break;
     case QUBO_TUNE_SEED_SWEEPS: t.seed_sweeps = value > 0 ? clampi(value, 1, 256) : (value < 0 ? 0 : d.seed_sweeps); break;
     case QUBO_TUNE_HALF_SCREEN: t.half_screen = value > 0 ? 1 : (value < 0 ? 0 : d.half_screen); break;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);

@@ -26,7 +26,8 @@ struct Views {
   uint32_t* umap;  // [umap_cap] work unit -> instance, or null (binary search)
   void* etab;      // log-partition: factor table b(t, j), layout of tab (float), or null
   double* tref;    // log-partition: min_j T'(g(t); j) + E_O(g(t)) per step, or null
-  int factor;      // log-partition: 1 = factored form allowed
+  int factor;      // log-partition: 0 direct form only; 1 factored form (the adjoint nested
+                   // where the factor rows allow); 2 factored form, per-state products
   uint64_t* dlist; // log-partition: units deferred to the direct-form pass, or null
   double* lanepart;  // sampling: per unit and lane, log2 of the lane's sum (forward walk output), or null
   int seed_sweeps; // descent passes of the threshold seed (0: no seeding)

@@ -586,6 +586,60 @@ __device__ __forceinline__ void block_moments(const float (&w)[kGradStates], flo
   s = h0 + h1;
 }
 
+// Nested form of the same sums.  Where a step's factor row is a product over
+// the inner bits, b(t, j) = b(t, 0) prod_{u in j} beta_u(t), the block sums are
+// b(t, 0) times s = sum_j a_j prod_{u in j} beta_u and v_a = sum_j a_j j_a
+// prod_{u in j} beta_u: multilinear polynomials in beta with the lane's a_j
+// as coefficients.  Level u pairs the states that differ in bit u (c_i =
+// c_2i + beta_u c_2i+1), and v_u is beta_u times the odd members of level u
+// evaluated over the bits above u.  62 multiply-adds, every operand in a
+// register, against 32 broadcast products and 57 adds.
+template <int U, int N>
+__device__ __forceinline__ float poly_eval(const float* c, const float (&be)[kGradInner]) {
+  if constexpr (N == 1) {
+    return c[0];
+  } else {
+    float d[N / 2];
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) d[i] = __builtin_fmaf(be[U], c[2 * i + 1], c[2 * i]);
+    return poly_eval<U + 1, N / 2>(d, be);
+  }
+}
+__device__ __forceinline__ void block_nested(const float (&a)[kGradStates], const float (&be)[kGradInner], float& s,
+                                             float (&va)[kGradInner]) {
+  float p[16], o[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    p[i] = __builtin_fmaf(be[0], a[2 * i + 1], a[2 * i]);
+    o[i] = a[2 * i + 1];
+  }
+  va[0] = be[0] * poly_eval<1, 16>(o, be);
+  float q[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    q[i] = __builtin_fmaf(be[1], p[2 * i + 1], p[2 * i]);
+    o[i] = p[2 * i + 1];
+  }
+  va[1] = be[1] * poly_eval<2, 8>(o, be);
+  float r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = __builtin_fmaf(be[2], q[2 * i + 1], q[2 * i]);
+    o[i] = q[2 * i + 1];
+  }
+  va[2] = be[2] * poly_eval<3, 4>(o, be);
+  const float h0 = __builtin_fmaf(be[3], r[1], r[0]), h1 = __builtin_fmaf(be[3], r[3], r[2]);
+  va[3] = be[3] * __builtin_fmaf(be[4], r[3], r[1]);
+  va[4] = be[4] * h1;
+  s = __builtin_fmaf(be[4], h1, h0);
+}
+
+// The nested form needs b(t, 0) >= 2^-40 at every step of the unit: then
+// beta_u = b(t, 2^u) / b(t, 0) <= 2^40 and so is every partial product.
+constexpr float kNestedMinB0 = 0x1p-40f;
+// Steps of the adjoint's table rows in flight ahead of the step being summed.
+constexpr int kPrefetch = 2;
+
 __device__ __forceinline__ int pidx(int n, int i, int j) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
 // The moments of a unit in the order the adjoint sums them: pairs of positions
@@ -714,10 +768,25 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
     // sum_j w(t, j) j_a; direct form: W[j] += w(t, j); factored form: the
     // step factor g in gs.  The caller has moved K / Pg to step t.
     const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_body
+    // fc: 0 direct form, 1 factored form with per-state products, 2 factored
+    // form nested (hs: the step's nested-form operands)
     auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1], float& gs) {
       float w[kGradStates];
       float va[kGradInner];
-      if constexpr (decltype(fc)::value) {
+      if constexpr (decltype(fc)::value == 2) {
+        const float g = exp2_fast((float)(sc + Pg));
+        gs = g;
+        // b(t, 0) and b(t, 2^u) broadcast from lanes 0, 1, 2, 4, 8 (x) and 0 (y)
+        // of each row
+        const float b0 = row_bcast<0>(tc.x), rb = __builtin_amdgcn_rcpf(b0);
+        const float be[kGradInner] = {row_bcast<1>(tc.x) * rb, row_bcast<2>(tc.x) * rb, row_bcast<4>(tc.x) * rb,
+                                      row_bcast<8>(tc.x) * rb, row_bcast<0>(tc.y) * rb};
+        block_nested(C, be, y[0], va);
+        const float gh = g * b0;
+        y[0] *= gh;
+#pragma unroll
+        for (int c = 0; c < kGradInner; ++c) y[1 + c] = va[c] * gh;
+      } else if constexpr (decltype(fc)::value == 1) {
         // sc = -bb (min_j T' + E_O)(t); weight = g * a_j * b(t, j) <= 1, g <= 2^kSafeExp2
         const float g = exp2_fast((float)(sc + Pg));
         gs = g;
@@ -837,6 +906,12 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
           for (int lo = 0; lo < 3; ++lo) Bo[l * (l - 1) / 2 + lo] = __builtin_fmaf(sgn, TL[lo], Bo[l * (l - 1) / 2 + lo]);
         };
         const uint32_t groups = steps >> 3;
+        f32x2 tq[kPrefetch];
+        double sq[kPrefetch];
+        tq[0] = tn;
+        sq[0] = sn;
+#pragma unroll
+        for (int d = 1; d < kPrefetch; ++d) fetch(d, tq[d], sq[d]);
         for (uint32_t q = 0; q < groups; ++q) {
           const bool qodd = q & 1;
           if (q) {
@@ -860,9 +935,15 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
   #pragma unroll
           for (int r = 0; r < 8; ++r) {
             const uint32_t t = 8 * q + r;
-            const f32x2 tc = tn;
-            const double sc = sn;
-            fetch(t + 1, tn, sn);
+            // operands kPrefetch steps ahead (the loads' latency exceeds a step)
+            const f32x2 tc = tq[0];
+            const double sc = sq[0];
+#pragma unroll
+            for (int d = 0; d + 1 < kPrefetch; ++d) {
+              tq[d] = tq[d + 1];
+              sq[d] = sq[d + 1];
+            }
+            fetch(t + kPrefetch, tq[kPrefetch - 1], sq[kPrefetch - 1]);
             if (r == 0) {
               if (q) kflip(3 + __builtin_ctz(q), (q >> (__builtin_ctz(q) + 1)) & 1);
             } else if (r == 4) {
@@ -928,7 +1009,24 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
         }
       }
     };
-    walk(std::integral_constant<bool, fac>{});
+    if constexpr (fac) {
+      // the nested form where the unit's factor rows allow it (every step
+      // shares the check: steps <= 2^kGradMaxOuter = 4 x 64)
+      static_assert(kGradMaxOuter <= 8, "four step rows per lane");
+      float mb = __builtin_inff();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = (uint32_t)lane + 64u * i;
+        if (t < steps)
+          mb = fminf(mb, __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(trs, (int)(t * 128u), 0, 0)));
+      }
+      if (v.factor == 1 && ballot(!(mb >= kNestedMinB0)) == 0)
+        walk(std::integral_constant<int, 2>{});
+      else
+        walk(std::integral_constant<int, 1>{});
+    } else {
+      walk(std::integral_constant<int, 0>{});
+    }
     if constexpr (fac) {
       // W[j] = a_j U(j, lane): a half-wave swap of the tiles' element e puts
       // inner states (e%4) + 8 (e/4) and 4 more of the lane's own column in x, y
