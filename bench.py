@@ -421,7 +421,7 @@ def valu_rates():
     P.valu_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     P.valu_rate_form_name.restype = ctypes.c_char_p
-    for wps in (4, 8):
+    for wps in (2, 4, 8):
         for form in range(P.valu_rate_forms()):
             ms, mhz, cyc = ctypes.c_float(), ctypes.c_double(), ctypes.c_double()
             rc = P.valu_rate(form, wps, 20000, ctypes.byref(ms), ctypes.byref(mhz), ctypes.byref(cyc))
