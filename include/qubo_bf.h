@@ -300,9 +300,12 @@ const char* qubo_version(void);
  *                                 with per-state products in the gradient
  *                                 walk; -1: always one exp per state (same
  *                                 results within rounding)
- *   QUBO_TUNE_SEED_SWEEPS         descent passes of the per-instance threshold
- *                                 seed before a top-k walk; -1: no seeding
- *                                 (speed only: results are identical)
+ *   QUBO_TUNE_SEED_SWEEPS         steepest descents (1 .. 64, default 4) of
+ *                                 the per-instance threshold seed before a
+ *                                 top-k walk, spread over the instance's waves
+ *                                 (one in a batch, four for a single solve);
+ *                                 -1: no seeding (speed only: results are
+ *                                 identical)
  *   QUBO_TUNE_HALF_SCREEN         top-k walks: 1 screens each block of 64
  *                                 states of float32, float64 and int64 Q in
  *                                 packed float16 (with a margin that keeps

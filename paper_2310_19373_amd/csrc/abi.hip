@@ -49,7 +49,7 @@ struct Tuning {
   int chunk_batched = 2;
   int dyn = 1;
   int logz_factored = 1;
-  int seed_sweeps = 1;
+  int seed_sweeps = 4;
   int half_screen = 1;
 };
 
@@ -72,6 +72,7 @@ Tuning& tuning() {
     d.dyn = env_int("QUBO_BF_DYNAMIC_QUEUE", d.dyn);
     d.logz_factored = env_int("QUBO_BF_LOGZ_FACTORED", d.logz_factored);
     d.seed_sweeps = env_int("QUBO_BF_SEED_SWEEPS", d.seed_sweeps);
+    d.seed_sweeps = d.seed_sweeps < 0 ? 0 : (d.seed_sweeps > 64 ? 64 : d.seed_sweeps);
     d.half_screen = env_int("QUBO_BF_HALF_SCREEN", d.half_screen);
     return d;
   }();
@@ -426,7 +427,7 @@ int qubo_bf_set_tuning(int knob, int value) {
     case QUBO_TUNE_CHUNK_BATCHED: t.chunk_batched = value > 0 ? value : d.chunk_batched; break;
     case QUBO_TUNE_DYNAMIC_QUEUE: t.dyn = value > 0 ? 1 : (value < 0 ? 0 : d.dyn); break;
     case QUBO_TUNE_LOGZ_FACTORED: t.logz_factored = value > 0 ? clampi(value, 1, 2) : (value < 0 ? 0 : d.logz_factored); break;
-    case QUBO_TUNE_SEED_SWEEPS: t.seed_sweeps = value > 0 ? clampi(value, 1, 256) : (value < 0 ? 0 : d.seed_sweeps); break;
+    case QUBO_TUNE_SEED_SWEEPS: t.seed_sweeps = value > 0 ? clampi(value, 1, 64) : (value < 0 ? 0 : d.seed_sweeps); break;
     case QUBO_TUNE_HALF_SCREEN: t.half_screen = value > 0 ? 1 : (value < 0 ? 0 : d.half_screen); break;
     default: return fail(QUBO_ERR_INVALID_ARG, "unknown tuning knob %d", knob);
   }

@@ -30,7 +30,7 @@ struct Views {
                    // where the factor rows allow); 2 factored form, per-state products
   uint64_t* dlist; // log-partition: units deferred to the direct-form pass, or null
   double* lanepart;  // sampling: per unit and lane, log2 of the lane's sum (forward walk output), or null
-  int seed_sweeps; // descent passes of the threshold seed (0: no seeding)
+  int seed_sweeps; // steepest descents per instance of the threshold seed (0: no seeding)
   int64_t umap_cap;
   int batch, nmax;
   int dyn;         // 1: atomic work queue, 0: static round-robin of chunks

@@ -347,47 +347,40 @@ __device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
   return (a0 + a1) + (a2 + a3);
 }
 
-// The same for a float32 row, 16-byte LDS loads (np is a multiple of 4 and
-// rows start 16-byte aligned), summed in the same order as field().
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float field_f4(const float* row, int np, uint64_t x) {
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  int j = 0;
-  // 16 entries per step: four loads in flight before their sums (one wave per
-  // SIMD runs this chain, so the LDS latency is not hidden by other waves)
-  for (; j + 16 <= np; j += 16) {
-    f32x4_t r[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) r[c] = *(const f32x4_t*)(row + j + 4 * c);
-    const uint32_t bits = (uint32_t)(x >> j);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      a0 += ((bits >> (4 * c)) & 1u) ? r[c].x : 0.f;
-      a1 += ((bits >> (4 * c)) & 2u) ? r[c].y : 0.f;
-      a2 += ((bits >> (4 * c)) & 4u) ? r[c].z : 0.f;
-      a3 += ((bits >> (4 * c)) & 8u) ? r[c].w : 0.f;
-    }
-  }
-  for (; j < np; j += 4) {
-    const f32x4_t r = *(const f32x4_t*)(row + j);
-    const uint32_t bits = (uint32_t)(x >> j);
-    a0 += (bits & 1u) ? r.x : 0.f;
-    a1 += (bits & 2u) ? r.y : 0.f;
-    a2 += (bits & 4u) ? r.z : 0.f;
-    a3 += (bits & 8u) ? r.w : 0.f;
-  }
-  return (a0 + a1) + (a2 + a3);
+constexpr int kSeedThreads = 256;  // a single instance's seed: four waves of descents
+
+// Every lane gets the wave's minimum / sum: DPP within each row of 16 lanes
+// (xor 1, xor 2, half-row and row mirrors), then the four rows by lane reads.
+template <int Ctrl>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_f32(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ __forceinline__ float wave_min_f32(float v) {
+  v = fminf(v, dpp_mov<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = fminf(v, dpp_mov<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = fminf(v, dpp_mov<0x141>(v));  // row_half_mirror
+  v = fminf(v, dpp_mov<0x140>(v));  // row_mirror
+  return fminf(fminf(lane_f32(v, 0), lane_f32(v, 16)), fminf(lane_f32(v, 32), lane_f32(v, 48)));
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  return (lane_f32(v, 0) + lane_f32(v, 16)) + (lane_f32(v, 32) + lane_f32(v, 48));
 }
 
-constexpr int kSeedThreads = 256;  // descents of a single instance (one per thread)
-
-// A-priori threshold for instance b.  Each thread (64 or 256) runs a greedy
-// one-flip descent from its own start (thread 0 from x = 0).  The best local
-// minimum x*, its n one-flip and n(n-1)/2 two-flip neighbours are distinct
-// states, so the K'-th smallest of their values bounds the instance's K'-th
-// smallest value from above.  Published with the float filter's error margin,
-// the bound discards nothing the walk would keep; it only spares each wave the
-// replays of its cold start.  A prefix-range solve keeps its top seed_fix bits
+// A-priori threshold for instance b.  Its waves (one or four) run
+// `seed_sweeps` steepest one-flip descents between them, from their own starts
+// (wave 0's first from x = 0): lane j holds the field h_j = sum_i S_ij x_i of bit j in float32,
+// every step flips the bit with the most negative change (a wave minimum) and
+// moves the fields by one row of S, until no flip lowers f or 4n steps have
+// been taken.  The best local minimum x*, its n one-flip and n(n-1)/2 two-flip
+// neighbours are distinct states, so the K'-th smallest of their values bounds
+// the instance's K'-th smallest value from above.  Published with the float
+// filter's error margin, the bound discards nothing the walk would keep; it
+// only spares each wave the replays of its cold start.  A prefix-range solve keeps its top seed_fix bits
 // at the range's first prefix and descends over the free bits only, so that
 // x* and its free-bit neighbours lie in the range and bound the range's K'-th
 // smallest value.
@@ -439,32 +432,38 @@ __device__ void seed_role(const Views& v, int b, unsigned char* seed_lds) {
   __syncthreads();
   const uint64_t free = nf >= 64 ? ~0ull : ((1ull << nf) - 1);
   const uint64_t base = fix > 0 ? ((uint64_t)I->local_off >> (I->tb - fix)) << nf : 0;
-  uint64_t x = base | (tid == 0 ? 0 : (mix64(((uint64_t)b << 8) | (uint64_t)tid) & free));
-  // descent in float32 (any states back the bound, so neither convergence nor
-  // exact deltas matter here): at most `sweeps` passes over the bits
-  const int sweeps = v.seed_sweeps < 4 * n ? v.seed_sweeps : 4 * n;
-  for (int sweep = 0; sweep < sweeps; ++sweep) {
-    bool moved = false;
-    for (int i = 0; i < nf; ++i) {
-      const float g = df[i] + field_f4(sf + i * np, np, x);
-      if ((((x >> i) & 1) ? -g : g) < 0.f) {
-        x ^= 1ull << i;
-        moved = true;
-      }
+  // descents in float32 (any states back the bound, so neither exact deltas
+  // nor convergence matter here); lanes j >= nf never flip
+  const int runs = (v.seed_sweeps + nwv - 1) / nwv;  // the instance's descents, spread over its waves
+  const float dj = lane < n ? df[lane] : 0.f;
+  float bf = __builtin_inff();
+  uint64_t bx = base;
+  for (int run = 0; run < runs; ++run) {
+    const int id = w * runs + run;
+    uint64_t x = base | (id == 0 ? 0 : (mix64(((uint64_t)b << 8) | (uint64_t)id) & free));
+    float h = 0.f;  // h_j of lane j < n
+    if (lane < n)
+      for (int i = 0; i < n; ++i)
+        if ((x >> i) & 1) h += sf[i * np + lane];
+    for (int step = 0; step < 4 * n; ++step) {
+      const float g = dj + h;
+      const float dlt = lane < nf ? (((x >> lane) & 1) ? -g : g) : __builtin_inff();
+      const float m = wave_min_f32(dlt);
+      if (!(m < 0.f)) break;
+      const int j = __builtin_ctzll(ballot(dlt == m));
+      x ^= 1ull << j;
+      if (lane < n) h += ((x >> j) & 1) ? sf[j * np + lane] : -sf[j * np + lane];
     }
-    if (!moved) break;
+    // f(x) = sum_j x_j (d_j + h_j / 2); the wave's best, ties to the lower x
+    const float fx = wave_sum_f32(((x >> lane) & 1) && lane < n ? dj + 0.5f * h : 0.f);
+    if (fx < bf || (fx == bf && x < bx)) {
+      bf = fx;
+      bx = x;
+    }
   }
-  // best local minimum of each wave by its float32 value, ties to the lower
-  // lane, then the best of the waves, ties to the lower wave
-  float fx = 0.f;
-  for (int i = 0; i < n; ++i)
-    if ((x >> i) & 1) fx += df[i] + 0.5f * field_f4(sf + i * np, np, x);
-  double key = (double)fx;
-  uint64_t mask = x;
-  wave_sort(key, mask, lane);
   if (lane == 0) {
-    best_f[w] = (float)key;
-    best_x[w] = mask;
+    best_f[w] = bf;
+    best_x[w] = bx;
   }
   __syncthreads();
   if (w != 0) return;
@@ -487,8 +486,8 @@ __device__ void seed_role(const Views& v, int b, unsigned char* seed_lds) {
   // first K' form the candidate list
   const W si = ((xs >> lane) & 1) ? (W)-1 : (W)1;
   const W Di = lane < nf ? si * gi : (W)0;
-  key = __builtin_inf();
-  mask = ~0ull;
+  double key = __builtin_inf();
+  uint64_t mask = ~0ull;
   if (lane < nf) {
     mask = xs ^ (1ull << lane);
     key = (double)(tot + Di);

@@ -1,7 +1,7 @@
 """Speed-only tuning knobs leave every output bit-identical.
 
 Work distribution (dynamic XCD-segmented queue vs static round-robin, chunk
-caps), the threshold seed (on, off, more descent passes), the launch shape
+caps), the threshold seed (on, off, more descents), the launch shape
 (outer bits, waves per CU) and the float32 walk's block screen (packed float16
 or float32) change which wave walks which states and when, never the results.  Each case compares against the default setting and, on
 small sizes, against the oracle.
