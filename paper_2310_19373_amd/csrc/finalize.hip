@@ -98,12 +98,16 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
                                                              int k, typename Rescore<Qin>::En* energies,
                                                              uint64_t* masks, int32_t* status) {
   using En = typename Rescore<Qin>::En;
-  __shared__ double sk[kMaxFinWaves][kWave];
-  __shared__ uint64_t sm[kMaxFinWaves][kWave];
-  __shared__ Qin sq[64 * 64];  // the instance's n x n block, row stride n
-  __shared__ En se[kMaxKPrime];
+  // LDS sized to the launch (fin_lds_bytes): the waves' lists, the rescored
+  // energies and the instance's n x n block of Q (row stride n <= nmax), so
+  // that a batch's one-wave blocks are not held to a few per CU
+  extern __shared__ __attribute__((aligned(16))) unsigned char fin_lds[];
   const int b = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double(*const sk)[kWave] = (double(*)[kWave])fin_lds;
+  uint64_t(*const sm)[kWave] = (uint64_t(*)[kWave])(fin_lds + (size_t)nw * kWave * sizeof(double));
+  En* const se = (En*)(fin_lds + (size_t)nw * kWave * (sizeof(double) + sizeof(uint64_t)));
+  Qin* const sq = (Qin*)(se + kMaxKPrime);
   const Inst* I = &v.inst[b];
   const int kp = I->kprime;
   const int32_t st0 = I->status;
@@ -266,21 +270,25 @@ hipError_t launch_finalize_topk(const Views& v, const void* q, int64_t ldq, int6
                                 hipStream_t s) {
   const int w = max(1, min(kMaxFinWaves, waves_per_inst));
   const dim3 g(v.batch), blk(64 * w);
+  // bytes of fin_lds: w lists of 64 (key, mask), kMaxKPrime energies, nmax^2 entries of Q
+  auto lds = [&](size_t qbytes) {
+    return (size_t)w * kWave * (sizeof(double) + sizeof(uint64_t)) + kMaxKPrime * 8 + (size_t)v.nmax * v.nmax * qbytes;
+  };
   switch (dt) {
     case kDtI32:
-      hipLaunchKernelGGL(finalize_topk_kernel<int32_t>, g, blk, 0, s, v, (const int32_t*)q, ldq, stride, k,
+      hipLaunchKernelGGL(finalize_topk_kernel<int32_t>, g, blk, lds(4), s, v, (const int32_t*)q, ldq, stride, k,
                          (int64_t*)energies, masks, status);
       break;
     case kDtF64:
-      hipLaunchKernelGGL(finalize_topk_kernel<double>, g, blk, 0, s, v, (const double*)q, ldq, stride, k,
+      hipLaunchKernelGGL(finalize_topk_kernel<double>, g, blk, lds(8), s, v, (const double*)q, ldq, stride, k,
                          (double*)energies, masks, status);
       break;
     case kDtI64:
-      hipLaunchKernelGGL(finalize_topk_kernel<int64_t>, g, blk, 0, s, v, (const int64_t*)q, ldq, stride, k,
+      hipLaunchKernelGGL(finalize_topk_kernel<int64_t>, g, blk, lds(8), s, v, (const int64_t*)q, ldq, stride, k,
                          (int64_t*)energies, masks, status);
       break;
     default:
-      hipLaunchKernelGGL(finalize_topk_kernel<float>, g, blk, 0, s, v, (const float*)q, ldq, stride, k,
+      hipLaunchKernelGGL(finalize_topk_kernel<float>, g, blk, lds(4), s, v, (const float*)q, ldq, stride, k,
                          (double*)energies, masks, status);
   }
   return hipGetLastError();
