@@ -325,9 +325,24 @@ __device__ __forceinline__ void wait_rows() {
 // kRowStride: HalfRow units between consecutive step rows (1: the float
 // layout; kInt16RowStride: an int32 instance beyond the int32 walk's range,
 // whose rows sit in the int32 layout's 256-byte step slots).
+// Issue priority by progress through the unit, for launches with about one
+// unit per wave: a SIMD issues from the ready wave of highest priority (then
+// the oldest), so without this the waves sharing it finish their units one
+// after another and the last ones run alone, at one wave's issue rate.  A
+// wave that is ahead yields to those behind it: priority 3 in the first
+// quarter of its steps, down to 0 in the last.
+__device__ __forceinline__ void pace(uint32_t done, uint32_t total) {
+  const uint32_t quarter = (4 * done) / total;
+  if (quarter == 0) __builtin_amdgcn_s_setprio(3);
+  else if (quarter == 1) __builtin_amdgcn_s_setprio(2);
+  else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 template <int kRowStride = 1>
 __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU& I, uint64_t local, double& lkey,
-                                              uint64_t& lmask, uint64_t& pub, double* myc, int lane) {
+                                              uint64_t& lmask, uint64_t& pub, double* myc, int lane,
+                                              bool paced = false) {
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
   const double hs = uniform_f64(gp((const Inst*)v.inst)[b].hscale);
@@ -446,6 +461,7 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
   };
   // every group but the last ends with steps 8q+7 and 8q+8 (the flip of bit
   // 3 + CTZ(q+1)); the last group, peeled, ends with step 8q+7
+  if (paced) __builtin_amdgcn_s_setprio(3);
   for (uint32_t q = 0; q + 1 < groups; ++q) {
     six(q);
     const uint32_t t = 8 * q;
@@ -467,6 +483,7 @@ __device__ __forceinline__ void walk_unit_h16(const Views& v, int b, const InstU
       const double g = load_gthr(v, b);
       if (enc_key(g) < pub) pub = enc_key(g);
       if (g < thr) retune(g);
+      if (paced) pace(q + 1, groups);
     }
   }
   six(groups - 1);
@@ -510,7 +527,8 @@ __device__ __forceinline__ int32_t int16_block_min(const HalfRow& r, const s2 (&
 }
 
 __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU& I, uint64_t local, double& lkey,
-                                              uint64_t& lmask, uint64_t& pub, int64_t* myc, int lane) {
+                                              uint64_t& lmask, uint64_t& pub, int64_t* myc, int lane,
+                                              bool paced = false) {
   const bool valid = lane < (1 << I.L);
   const uint64_t p = (local << I.L) | (uint64_t)lane;
   // C'(j), j = c | a << 4, as int16 pairs (a, a + 2); invalid entries 32767
@@ -612,6 +630,7 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
     flip_off(c1);
     body(t + 6, ev);
   };
+  if (paced) __builtin_amdgcn_s_setprio(3);
   for (uint32_t q = 0; q + 1 < groups; ++q) {
     six(q);
     const uint32_t t = 8 * q;
@@ -633,6 +652,7 @@ __device__ __forceinline__ void walk_unit_i16(const Views& v, int b, const InstU
       const double g = load_gthr(v, b);
       if (enc_key(g) < pub) pub = enc_key(g);
       if (g < thr) retune(g);
+      if (paced) pace(q + 1, groups);
     }
   }
   six(groups - 1);
@@ -653,6 +673,8 @@ __device__ __forceinline__ void walk_topk_body(const Views& v) {
   uint64_t pub = ~0ull;
   int cur = -1;
   WorkIter it(v, total_units);
+  // about one unit per wave: pace the waves of a SIMD (see pace)
+  const bool paced = total_units <= (uint64_t)gridDim.x * kWavesPerBlock;
   uint64_t u;
   while (it.next(v, lane, u)) {
     const int b = v.batch == 1 ? 0 : find_unit(v, u);
@@ -678,11 +700,11 @@ __device__ __forceinline__ void walk_topk_body(const Views& v) {
         }
       }
       if constexpr (kHalf && std::is_same_v<E, float>) {
-        walk_unit_h16(v, b, I, local, lkey, lmask, pub, myc, lane);
+        walk_unit_h16(v, b, I, local, lkey, lmask, pub, myc, lane, paced);
       } else if constexpr (kHalf) {
         // int16 screen where the instance's inner bound allows it
         if (uniform_f64(gp((const Inst*)v.inst)[b].hscale) != 0.0)
-          walk_unit_i16(v, b, I, local, lkey, lmask, pub, myc, lane);
+          walk_unit_i16(v, b, I, local, lkey, lmask, pub, myc, lane, paced);
         else
           walk_unit<E>(v, b, I, local, lkey, lmask, pub, myc, lane);
       } else {
