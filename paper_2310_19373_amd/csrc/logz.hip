@@ -17,8 +17,10 @@
 //     most kSafeExp2): the weight of state (t, j) splits as
 //       a_j * b(t, j) * 2^(c_t),  a_j = 2^(-bb (C'(j) - min C')),
 //       b(t, j) = 2^(-bb (T'(g(t); j) - min_j T'(g(t); .))),
-//     so a block of 64 states is one 64-term dot product (one DPP-broadcast
-//     FMA per state) and one exp per step.  The range bound keeps the block's
+//     so a lane's sum is sum_j a_j U_j with U_j = sum_t 2^(c_t) b(t, j): per
+//     wave a matrix product of the step rows and the lanes' step weights, on
+//     the matrix cores (one multiply-add per state), and one exp per step.
+//     The range bound keeps the block's
 //     largest product above 2^-kSafeExp2, so float32 underflow only drops
 //     terms below 2^-126 of an already represented block sum;
 //   * direct (other units): e_j = C'(j) + T'(g(t); j), the block minimum
@@ -32,7 +34,10 @@
 //   Bo[o1][o2]    = sum_t x_o1(t) x_o2(t) s(t)
 // (x_o(t) = bit o of g(t), uniform across lanes) and at the end of the unit
 // assembles the n(n+1)/2 moments sum w x_i x_j for the unit, the prefix bits
-// entering through the lane's own bits and the unit's tile bits.
+// entering through the lane's own bits and the unit's tile bits.  In the
+// factored form W comes from the matrix cores as in the forward (W = a_j U_j),
+// and s, v_a are nested multiply-adds over the inner bits where a step's row
+// factors into per-bit terms (block_nested).
 #include "walk.hpp"
 
 namespace qbf {
