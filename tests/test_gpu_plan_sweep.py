@@ -11,6 +11,7 @@ run reaches, and at n > 40.
   and 63, the range of 2^24 masks that holds x*: x* comes first with the
   oracle's energy and, where the oracle can run the range, the whole top-k
   equals the oracle's.
+* int64 and float64 Q at n = 63: a range of 2^20 masks against the oracle.
 """
 import numpy as np
 import pytest
@@ -110,3 +111,23 @@ def test_planted_beyond_40_by_the_range_holding_xstar(gpu_lib, n):
     e2, m2 = api.solve_range(Q, k, p_bits, q, q + 1)
     E2, M2 = oracle.topk(Q, k, lo=q << span, hi=(q + 1) << span)
     assert _u64(_np(m2)) == _u64(M2) and np.array_equal(_np(e2), E2)
+
+
+@pytest.mark.parametrize("dtype", [np.int64, np.float64])
+def test_wide_dtypes_at_n63_range_against_oracle(gpu_lib, dtype):
+    """int64 and float64 Q at n = 63, the widest mask: one prefix range of 2^20
+    masks, bit for bit against the oracle's top-k of the same block.  The merge
+    and rescoring launch then holds the largest n x n block of 8-byte Q."""
+    n, span, k = 63, 20, 16
+    rng = np.random.default_rng(6363 if dtype is np.int64 else 6364)
+    if dtype is np.int64:
+        Q = np.triu(rng.integers(-1000, 1001, (n, n))).astype(np.int64)
+    else:
+        Q = np.triu(rng.standard_normal((n, n)) / np.sqrt(n)).astype(np.float64)
+    p_bits = n - span
+    p = int(rng.integers(0, 1 << p_bits))
+    print(f"n=63 {np.dtype(dtype).name} range of prefix {p} (p_bits={p_bits})", flush=True)
+    e, m = api.solve_range(Q, k, p_bits, p, p + 1)
+    E, M = oracle.topk(Q, k, lo=p << span, hi=(p + 1) << span)
+    assert _u64(_np(m)) == _u64(M)
+    assert np.array_equal(_np(e), E)
