@@ -38,6 +38,7 @@
 // factored form W comes from the matrix cores as in the forward (W = a_j U_j),
 // and s, v_a are nested multiply-adds over the inner bits where a step's row
 // factors into per-bit terms (block_nested).
+#include "dpp.hpp"
 #include "walk.hpp"
 
 namespace qbf {
@@ -463,13 +464,26 @@ __global__ void __launch_bounds__(256) prep_exp_tables_kernel(Views v, const flo
   const float* tab = (const float*)v.tab + I->tab_off * width;
   float* etab = (float*)v.etab + I->tab_off * width;
   const int64_t c0 = (int64_t)blockIdx.y * 64;
-  for (int64_t t = c0 + w; t < steps && t < c0 + 64; t += 4) {
-    const float tv = lane < width ? tab[t * width + lane] : __builtin_inff();
-    float m = tv;
+  // the wave's 16 steps c0 + w + 4i: all rows and offsets loaded first (their
+  // latencies overlap), then per step one wave minimum (DPP, no LDS) and one
+  // exp per entry
+  constexpr int kPer = 16;
+  float tv[kPer];
+  double eo[kPer];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o));
-    if (lane < width) etab[t * width + lane] = exp2_fast(-bbf * (tv - m));
-    if (lane == 0) v.tref[I->tab_off + t] = -bb * ((double)m + v.eod[I->tab_off + t]);
+  for (int i = 0; i < kPer; ++i) {
+    const int64_t t = c0 + w + 4 * i;
+    const bool ok = t < steps;
+    tv[i] = ok && lane < width ? tab[t * width + lane] : __builtin_inff();
+    eo[i] = ok ? v.eod[I->tab_off + t] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int64_t t = c0 + w + 4 * i;
+    if (t >= steps) break;
+    const float m = wave_min_f32(tv[i]);
+    if (lane < width) etab[t * width + lane] = exp2_fast(-bbf * (tv[i] - m));
+    if (lane == 0) v.tref[I->tab_off + t] = -bb * ((double)m + eo[i]);
   }
 }
 

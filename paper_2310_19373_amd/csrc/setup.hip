@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "dpp.hpp"
 #include "launch.hpp"
 #include "wave.hpp"
 
@@ -348,28 +349,6 @@ __device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
 }
 
 constexpr int kSeedThreads = 256;  // a single instance's seed: four waves of descents
-
-// Every lane gets the wave's minimum / sum: DPP within each row of 16 lanes
-// (xor 1, xor 2, half-row and row mirrors), then the four rows by lane reads.
-template <int Ctrl>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float lane_f32(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
-__device__ __forceinline__ float wave_min_f32(float v) {
-  v = fminf(v, dpp_mov<0xB1>(v));   // quad_perm [1, 0, 3, 2]
-  v = fminf(v, dpp_mov<0x4E>(v));   // quad_perm [2, 3, 0, 1]
-  v = fminf(v, dpp_mov<0x141>(v));  // row_half_mirror
-  v = fminf(v, dpp_mov<0x140>(v));  // row_mirror
-  return fminf(fminf(lane_f32(v, 0), lane_f32(v, 16)), fminf(lane_f32(v, 32), lane_f32(v, 48)));
-}
-__device__ __forceinline__ float wave_sum_f32(float v) {
-  v += dpp_mov<0xB1>(v);
-  v += dpp_mov<0x4E>(v);
-  v += dpp_mov<0x141>(v);
-  v += dpp_mov<0x140>(v);
-  return (lane_f32(v, 0) + lane_f32(v, 16)) + (lane_f32(v, 32) + lane_f32(v, 48));
-}
 
 // A-priori threshold for instance b.  Its waves (one or four) run
 // `seed_sweeps` steepest one-flip descents between them, from their own starts
