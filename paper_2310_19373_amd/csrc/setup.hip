@@ -305,22 +305,55 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
 // S(u, a) for inner bits u, [8+k] = sum_{set lane bits a} S(B+k, a) for outer
 // bits k.
 template <class W>
-__device__ void lanes_role(const Views& v, int b, int l) {
+__device__ void lanes_role(const Views& v, int b, int l, W* st) {
+  // One wave: the entries of Q the records need are staged in LDS by
+  // independent loads (three per lane), so their latencies overlap; lane l
+  // then sums them for its set bits, in the order of a loop over the bits.
   const Inst* I = &v.inst[b];
   W* lt = (W*)v.lt + ((int64_t)b * 64 + l) * kLaneRec;
   W rec[kLaneRec];
   for (int i = 0; i < kLaneRec; ++i) rec[i] = 0;
-  if (I->status == 0 && l < (1 << I->L)) {
-    const int B = I->B, no = I->no, pos0 = B + no, nm = v.nmax;
+  if (I->status == 0) {
+    const int L = I->L, B = I->B, no = I->no, pos0 = B + no, nm = v.nmax;
     const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
-    for (int a = 0; a < I->L; ++a) {
-      if (!((l >> a) & 1)) continue;
-      const int ra = pos0 + a;
-      rec[0] += qs[(int64_t)ra * nm + ra];
-      for (int a2 = a + 1; a2 < I->L; ++a2)
-        if ((l >> a2) & 1) rec[0] += qs[(int64_t)ra * nm + pos0 + a2];
-      for (int u = 0; u < B && u < 6; ++u) rec[1 + u] += qs[(int64_t)u * nm + ra];
-      for (int k = 0; k < no && 8 + k < kLaneRec; ++k) rec[8 + k] += qs[(int64_t)(B + k) * nm + ra];
+    // column a of lane bit a (ra = pos0 + a): [0] Q(ra, ra), [1 + a2]
+    // Q(ra, pos0 + a2), [7 + u] Q(u, ra) for inner u, [13 + k] Q(B + k, ra)
+    // for outer k
+    constexpr int kCol = 13 + kMaxOuter;
+    static_assert(6 * kCol <= 3 * kWave, "three staged entries per lane");
+    W q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int e = l + kWave * d, a = e / kCol, f = e % kCol, ra = pos0 + a;
+      int row = -1, col = 0;
+      if (a < L) {
+        if (f == 0) row = ra, col = ra;
+        else if (f < 7) { if (f - 1 > a && f - 1 < L) row = ra, col = pos0 + f - 1; }
+        else if (f < 13) { if (f - 7 < B) row = f - 7, col = ra; }
+        else if (f - 13 < no) row = B + f - 13, col = ra;
+      }
+      q[d] = row >= 0 ? qs[(int64_t)row * nm + col] : (W)0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (l + kWave * d < 6 * kCol) st[l + kWave * d] = q[d];
+    __builtin_amdgcn_wave_barrier();
+    // fixed trip counts, so that rec stays in registers
+    static_assert(8 + kMaxOuter <= kLaneRec, "the record holds every outer field");
+    if (l < (1 << L)) {
+      for (int a = 0; a < L; ++a) {
+        if (!((l >> a) & 1)) continue;
+        const W* c = st + a * kCol;
+        rec[0] += c[0];
+        for (int a2 = a + 1; a2 < L; ++a2)
+          if ((l >> a2) & 1) rec[0] += c[1 + a2];
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+          if (u < B) rec[1 + u] += c[7 + u];
+#pragma unroll
+        for (int k = 0; k < kMaxOuter; ++k)
+          if (k < no) rec[8 + k] += c[13 + k];
+      }
     }
   }
   for (int i = 0; i < kLaneRec; ++i) lt[i] = rec[i];
@@ -533,10 +566,20 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
   const int64_t c0 = (int64_t)chunk * blockDim.x;
   if (c0 >= steps) return;
   const W* qs = (const W*)v.qs + (int64_t)b * nm * nm;
-  // row r < 6: inner row u = r; row 6 + l: outer row B + l; column l2: B + l2
-  for (int e = threadIdx.x; e < (6 + no) * no; e += blockDim.x) {
-    const int r = e / no, l2 = e % no;
-    qo[e] = (r < 6 && r >= B) ? (W)0 : qs[(int64_t)(r < 6 ? r : B + r - 6) * nm + B + l2];
+  // row r < 6: inner row u = r; row 6 + l: outer row B + l; column l2: B + l2;
+  // up to (6 + kMaxOuter) kMaxOuter entries, three loads per thread of a
+  // 64-thread block in flight together
+  const int nq = (6 + no) * no;
+  for (int e0 = threadIdx.x; e0 < nq; e0 += 3 * blockDim.x) {
+    W q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int e = e0 + d * blockDim.x, r = e / no, l2 = e % no;
+      q[d] = (e >= nq || (r < 6 && r >= B)) ? (W)0 : qs[(int64_t)(r < 6 ? r : B + r - 6) * nm + B + l2];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (e0 + d * blockDim.x < nq) qo[e0 + d * blockDim.x] = q[d];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -627,6 +670,7 @@ __device__ void tables_role(const Views& v, int b, int chunk, int inner, unsigne
   __builtin_amdgcn_wave_barrier();
   E* tab = (E*)v.tab + I->tab_off * width;
   const int nst = (int)(steps - s0 < kWave ? steps - s0 : kWave);
+#pragma unroll 4
   for (int k = 0; k < nst; ++k) {
     // H_u is zero for u >= B, so summing every set lane bit is the same sum
     W tj = 0;
@@ -646,7 +690,7 @@ __device__ void prep_walk_roles(const Views& v, int b, int role, int inner, int 
   if (role == 0) {
     if (seed_on) seed_role<W>(v, b, lds);
   } else if (role == 1) {
-    if (threadIdx.x < kWave) lanes_role<W>(v, b, threadIdx.x);
+    if (threadIdx.x < kWave) lanes_role<W>(v, b, threadIdx.x, (W*)lds);
   } else {
     tables_role<W, E, kWideI32>(v, b, role - 2, inner, lds);
   }
