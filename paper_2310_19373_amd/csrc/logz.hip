@@ -1187,7 +1187,18 @@ __global__ void finalize_grad_kernel(Views v, const float* q, const float* beta,
     float outv = 0.f;
     double M = 0.0;
     if (st == 0 && i <= j && j < n) {
-      for (int64_t u = 0; u < I->units; ++u) M += v.part[(I->unit_begin + u) * npairs + pidx(n, i, j)];
+      // the units in order, eight loads in flight ahead of their additions
+      const double* pu = v.part + I->unit_begin * npairs + pidx(n, i, j);
+      const int64_t nu = I->units;
+      int64_t u = 0;
+      for (; u + 8 <= nu; u += 8) {
+        double x[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) x[d] = pu[(u + d) * npairs];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) M += x[d];
+      }
+      for (; u < nu; ++u) M += pu[u * npairs];
       outv = (float)(g * -bt * M);
       mean += (double)Q[(int64_t)i * nm + j] * M;
     } else if (st != 0) {
