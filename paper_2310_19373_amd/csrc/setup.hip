@@ -228,14 +228,24 @@ __global__ void __launch_bounds__(256) prep_inst_kernel(Views v, const Qin* q, i
     if (wide) ((double*)qs)[(int64_t)i * nmax + j] = sgn * (double)val;
     else qs[(int64_t)i * nmax + j] = (W)(sgn * (double)val);
   }
-  // E_I(j) for the inner bits, straight from Eq. 1 restricted to bits < B.
+  // E_I(j) for the inner bits, straight from Eq. 1 restricted to bits < B;
+  // the inner block of Q (at most 6 x 6) is read once into LDS, one load per
+  // thread, and the sums keep their order
+  __shared__ W qin[6][6];
+  if (tid < 36) {
+    const int u = tid / 6, w = tid % 6;
+    qin[u][w] = (u < B && w < B && u <= w) ? (W)(sgn * (double)Q[(int64_t)u * ldq + w]) : (W)0;
+  }
+  __syncthreads();
   if (tid < (1 << inner)) {
     W e = 0;
-    for (int u = 0; u < B; ++u) {
-      if (!((tid >> u) & 1)) continue;
-      W row = (W)(sgn * (double)Q[(int64_t)u * ldq + u]);
-      for (int w = u + 1; w < B; ++w)
-        if ((tid >> w) & 1) row += (W)(sgn * (double)Q[(int64_t)u * ldq + w]);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      if (u >= B || !((tid >> u) & 1)) continue;
+      W row = qin[u][u];
+#pragma unroll
+      for (int w = u + 1; w < 6; ++w)
+        if (w < B && ((tid >> w) & 1)) row += qin[u][w];
       e += row;
     }
     if (wide) ((double*)v.ei)[(int64_t)b * 64 + tid] = (double)e;  // exact: |e| <= sum |Q|
