@@ -788,7 +788,7 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
     // step factor g in gs.  The caller has moved K / Pg to step t.
     const float nb = bb > 0.0 ? -bbf : -1e-30f;  // see walk_exp_body
     // fc: 0 direct form, 1 factored form with per-state products, 2 factored
-    // form nested (hs: the step's nested-form operands)
+    // form nested (its operands broadcast from the step row tc)
     auto block = [&](auto fc, const f32x2& tc, double sc, float (&y)[kGradInner + 1], float& gs) {
       float w[kGradStates];
       float va[kGradInner];
@@ -1064,9 +1064,10 @@ __device__ __forceinline__ void walk_grad_body(const Views& v, const float* beta
     // 32 at a time through this wave's lane-field table in LDS (free once the
     // walk is done): lane l stores its 32 values as row l, then sums column
     // l%32 over the rows of its half-wave, and a half-wave swap adds the two
-    // halves.  Lane l%32 carries the tag of value l%32: its output index and
-    // its stash slot (the diagonals of the positions below the tile bits and
-    // the unit's total are kept for the pairs with a tile bit).
+    // halves.  Lane l%32 then looks up value l%32's pair of positions in the
+    // slot table for its output index; the diagonals of the positions below
+    // the tile bits and the unit's total go to a stash after the rows, for
+    // the pairs with a tile bit.
     const int n = I.n, B = I.B, no = I.no, pos0 = B + no, L = I.L, m = pos0 + L;
     float st = 0.f, vt[kGradInner];
 #pragma unroll
