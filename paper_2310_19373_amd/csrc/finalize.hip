@@ -98,9 +98,9 @@ __global__ void __launch_bounds__(1024) finalize_topk_kernel(Views v, const Qin*
                                                              int k, typename Rescore<Qin>::En* energies,
                                                              uint64_t* masks, int32_t* status) {
   using En = typename Rescore<Qin>::En;
-  // LDS sized to the launch (fin_lds_bytes): the waves' lists, the rescored
-  // energies and the instance's n x n block of Q (row stride n <= nmax), so
-  // that a batch's one-wave blocks are not held to a few per CU
+  // LDS sized by the launch (launch_finalize_topk): the waves' lists, the
+  // rescored energies and the instance's n x n block of Q (row stride
+  // n <= nmax), so that a batch's one-wave blocks are not held to a few per CU
   extern __shared__ __attribute__((aligned(16))) unsigned char fin_lds[];
   const int b = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;

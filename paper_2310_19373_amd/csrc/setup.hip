@@ -394,18 +394,19 @@ __device__ __forceinline__ T field(const T* row, int np, uint64_t x) {
 constexpr int kSeedThreads = 256;  // a single instance's seed: four waves of descents
 
 // A-priori threshold for instance b.  Its waves (one or four) run
-// `seed_sweeps` steepest one-flip descents between them, from their own starts
-// (wave 0's first from x = 0): lane j holds the field h_j = sum_i S_ij x_i of bit j in float32,
-// every step flips the bit with the most negative change (a wave minimum) and
-// moves the fields by one row of S, until no flip lowers f or 4n steps have
-// been taken.  The best local minimum x*, its n one-flip and n(n-1)/2 two-flip
-// neighbours are distinct states, so the K'-th smallest of their values bounds
-// the instance's K'-th smallest value from above.  Published with the float
-// filter's error margin, the bound discards nothing the walk would keep; it
-// only spares each wave the replays of its cold start.  A prefix-range solve keeps its top seed_fix bits
-// at the range's first prefix and descends over the free bits only, so that
-// x* and its free-bit neighbours lie in the range and bound the range's K'-th
-// smallest value.
+// `seed_sweeps` steepest one-flip descents between them, from their own
+// starts (wave 0's first from x = 0): lane j holds the field
+// h_j = sum_i S_ij x_i of bit j in float32, every step flips the bit with the
+// most negative change (a wave minimum) and moves the fields by one row of S,
+// until no flip lowers f or 4n steps have been taken.  The best local minimum
+// x*, its n one-flip and n(n-1)/2 two-flip neighbours are distinct states, so
+// the K'-th smallest of their values bounds the instance's K'-th smallest
+// value from above.  Published with the float filter's error margin, the
+// bound discards nothing the walk would keep; it only spares each wave the
+// replays of its cold start.  A prefix-range solve keeps its top seed_fix
+// bits at the range's first prefix and descends over the free bits only, so
+// that x* and its free-bit neighbours lie in the range and bound the range's
+// K'-th smallest value.
 //
 // With S the symmetric off-diagonal part and d the diagonal,
 //   f(x) = sum_i x_i (d_i + h_i(x) / 2),  f(x ^ e_i) = f(x) + (1 - 2 x_i)(d_i + h_i(x)),
