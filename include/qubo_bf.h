@@ -112,7 +112,7 @@ int qubo_bf_solve(const void* Q, int n, int64_t ldq, qubo_dtype dt, int k, void*
 
 /*
  * qubo_bf_solve with the length K' of the candidate lists given: kprime in
- * [k, 64], or 0 for the default (max(2k, k + 8) capped at 64 for float Q, k
+ * [k, 64], or 0 for the default (max(2k, k + 3) capped at 64 for float Q, k
  * for integer Q).  A longer list gives the float certificate more room above
  * the k-th value (a solve whose status was QUBO_ERR_UNCERTAIN can be repeated
  * with kprime = 64), at a larger workspace: qubo_bf_workspace_size_kp, 0 for
