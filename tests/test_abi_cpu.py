@@ -157,6 +157,21 @@ def test_noalloc_rejects_before_any_hip_call(case):
     assert L.qubo_last_error()
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 16, 40, 56])
+def test_default_kprime_rule(k):
+    """Float Q keeps max(2k, k + 3) candidates by default (capped at 64),
+    integer Q keeps k: the default workspace is the one of that explicit K'
+    and smaller than the one of K' + 1."""
+    L = _lib.lib()
+    want = min(max(2 * k, k + 3), 64)
+    for n in (20, 40):
+        assert L.qubo_bf_workspace_size(n, k, 0) == L.qubo_bf_workspace_size_kp(n, k, want, 0)
+        if want < 64:
+            assert L.qubo_bf_workspace_size(n, k, 0) < L.qubo_bf_workspace_size_kp(n, k, want + 1, 0)
+        assert L.qubo_bf_workspace_size(n, k, 1) == L.qubo_bf_workspace_size_kp(n, k, k, 1)
+        assert L.qubo_bf_workspace_size(n, k, 1) < L.qubo_bf_workspace_size_kp(n, k, k + 1, 1)
+
+
 def test_kprime_argument_checks():
     L = _lib.lib()
     assert L.qubo_bf_workspace_size_kp(20, 4, 0, 0) == L.qubo_bf_workspace_size(20, 4, 0)
